@@ -1,0 +1,210 @@
+/*
+ * wcl.h -- C ABI of the MI355X (gfx950) Wilson-clover RAS solver library.
+ *
+ * The library solves the quark linear system D phi = eta (Sec. 1, Eq. (1))
+ * for the O(a)-improved Wilson (clover) operator with parameters kappa and
+ * c_SW (Sec. 5), using BiCGStab right-preconditioned by the restricted
+ * additive Schwarz iteration K_RAS (Sec. 2, Algorithm 1, Eqs. (2)-(3))
+ * inside a mixed-precision nested BiCGStab (Sec. 3): FP64 outer solver,
+ * FP32 inner solver, RAS domain solves in FP32 or FP16 storage.
+ *
+ * Operator (the paper names it but prints no formula; kappa-normalised
+ * standard form, chiral gamma basis, periodic links):
+ *   (D psi)(x) = [1 + c_SW kappa C(x)] psi(x)
+ *                - kappa sum_mu [ (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                               + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu) ]
+ *   C(x) = i sum_{mu<nu} sigma_{mu nu} Fhat_{mu nu}(x), Fhat from the four
+ *   plaquette leaves, (1/8)[(Q - Q^dag) - (1/3) Tr(Q - Q^dag)].
+ *   gamma_k = [[0,-i sigma_k],[i sigma_k,0]] (k = x,y,z), gamma_t = [[0,-1],[-1,0]].
+ *
+ * Conventions
+ *   - Every function returns an int status: WCL_OK (0) or a negative error
+ *     code; wcl_last_error() returns a thread-local message for the last
+ *     failure on the calling thread.  WCL_PENDING (> 0) is returned only by
+ *     wcl_poll.
+ *   - Host layouts are FP64 complex, array-of-structures, canonical site
+ *     index x + Lx*(y + Ly*(z + Lz*t)); directions mu = 0,1,2,3 = x,y,z,t:
+ *       gauge   double[V][4][3][3][2]   (site, mu, row, col, re/im)
+ *       spinor  double[nrhs][V][4][3][2] (rhs, site, spin, colour, re/im)
+ *   - Device spinor buffers are caller-owned (e.g. torch tensors), in the
+ *     library's internal structure-of-arrays layout for their precision,
+ *     which only wcl_pack_spinor* produce and wcl_unpack_spinor* read.
+ *     Their size is wcl_spinor_bytes(); alignment must be 256 bytes (any
+ *     hipMalloc / torch CUDA allocation satisfies it).
+ *   - Streams are HIP streams (hipStream_t passed as void*; NULL = default
+ *     stream).  Calls that take a stream are asynchronous on it unless
+ *     stated otherwise.
+ *   - Handles are not thread-safe, except wcl_submit / wcl_poll.
+ *   - The library owns the resident gauge and clover fields and all solver
+ *     workspace; it frees them in wcl_destroy_lattice / wcl_finalize.
+ */
+#ifndef WCL_H
+#define WCL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define WCL_OK 0
+#define WCL_EINVAL (-1)       /* invalid argument (shape, size, NaN/Inf input, ...) */
+#define WCL_ENOMEM (-2)       /* HBM budget or device allocation exhausted */
+#define WCL_EUNITARITY (-3)   /* gauge link not SU(3) to 1e-12 */
+#define WCL_ENOTCONV (-4)     /* solver hit its iteration limit; best iterate returned */
+#define WCL_EBREAKDOWN (-5)   /* BiCGStab breakdown persisted after restarts */
+#define WCL_EHIP (-6)         /* HIP runtime error */
+#define WCL_ESTATE (-7)       /* call out of order (e.g. no gauge uploaded) */
+#define WCL_PENDING 1         /* wcl_poll: request not finished yet */
+
+/* ---- precisions ---- */
+#define WCL_F64 0
+#define WCL_F32 1
+#define WCL_F16 2   /* binary16 storage, per-site FP32 scale for spinors/clover, FP32 arithmetic */
+
+/* ---- RAS domain solver kernels ---- */
+#define WCL_BLOCK_AUTO 0
+#define WCL_BLOCK_FUSED 1   /* one workgroup per (domain, rhs), LDS-resident (extended volume <= 1024) */
+#define WCL_BLOCK_SPLIT 2   /* several workgroups per domain, one launch per MR step (any shape) */
+
+typedef struct wcl_ctx wcl_ctx;
+typedef struct wcl_lattice wcl_lattice;
+typedef struct wcl_server wcl_server;
+
+/* RAS parameters (Sec. 2): domains Omega_i are the tiling of the lattice by
+ * `block` from the origin; Omega'_i grows each domain by s sites per side in
+ * every direction it does not span (overlap depth d = 2s, Sec. 4).
+ * n_ras sweeps of Algorithm 1, each domain solved approximately by n_dominv
+ * minimal-residual steps from zero (the paper's fixed-iteration domain
+ * solver).  storage = WCL_F32 or WCL_F16 for the gauge/clover fields and the
+ * sweep-internal residual/correction fields. */
+typedef struct wcl_ras_params {
+    int block[4];
+    int s;
+    int n_ras;
+    int n_dominv;
+    int storage;
+    int kernel;     /* WCL_BLOCK_* */
+} wcl_ras_params;
+
+#define WCL_PRECOND_NONE 0
+#define WCL_PRECOND_RAS 1
+
+/* Nested solver parameters (Sec. 3): the outer FP64 BiCGStab stops when its
+ * recursive residual is below tol_outer*|eta|, then recomputes the true
+ * residual |eta - D phi|/|eta| in FP64 and restarts from phi if it is above
+ * tol_outer (at most max_restarts times).  Each outer preconditioner call
+ * is an FP32 BiCGStab (right-preconditioned by K_RAS if precond = RAS) that
+ * stops at relative residual tol_inner or max_inner iterations. */
+typedef struct wcl_solver_params {
+    double tol_outer;
+    double tol_inner;
+    int max_outer;
+    int max_inner;
+    int max_restarts;
+    int precond;            /* WCL_PRECOND_* */
+    wcl_ras_params ras;
+} wcl_solver_params;
+
+/* Per-solve statistics.  ms_* are HIP-event times of the categories of the
+ * paper's timing chart (Sec. 4/5) as they exist on one device. */
+typedef struct wcl_solve_stats {
+    int outer_iters;
+    int inner_iters;        /* summed over all inner solves */
+    int restarts;           /* true-residual restarts + breakdown restarts */
+    int converged;
+    int64_t dslash_full;    /* full-lattice D applications (all precisions) */
+    int64_t dslash_block;   /* domain-solver MR steps (each = one D_Omega' over all domains) */
+    int64_t ras_sweeps;
+    double true_resid;      /* |eta - D phi| / |eta| in FP64 at exit */
+    double ms_total;
+} wcl_solve_stats;
+
+/* ---- context and lattice ---- */
+
+/* Opens `device` (HIP ordinal) with an HBM budget for everything the library
+ * allocates (0 = free memory at init).  *ctx receives the handle. */
+int wcl_init(int device, uint64_t hbm_budget_bytes, wcl_ctx** ctx);
+int wcl_finalize(wcl_ctx* ctx);
+const char* wcl_last_error(void);
+/* Bytes currently allocated by the library on the context's device. */
+uint64_t wcl_bytes_in_use(wcl_ctx* ctx);
+
+/* A lattice of dims = {Lx,Ly,Lz,Lt} (each >= 2) with fermion boundary phase
+ * bc[mu] = +1 (periodic) or -1 (antiperiodic); bc == NULL means periodic. */
+int wcl_create_lattice(wcl_ctx* ctx, const int dims[4], const int bc[4], wcl_lattice** lat);
+int wcl_destroy_lattice(wcl_lattice* lat);
+int64_t wcl_volume(const wcl_lattice* lat);
+
+/* Uploads U (host gauge layout above), checks |U U^dag - 1| and |det U - 1|
+ * <= 1e-12 for every link (WCL_EUNITARITY otherwise), stores it on the
+ * device as two-row (12-real) links in FP64, FP32 and FP16.  Synchronous.
+ * The clover field of the previous gauge, if any, is invalidated. */
+int wcl_upload_gauge(wcl_lattice* lat, const double* U);
+/* Builds C(x) = i sum sigma Fhat on the device from the resident links and
+ * stores it (kappa-independent) as two packed 6x6 Hermitian blocks per site in
+ * FP64, FP32 and FP16.  Synchronous. */
+int wcl_compute_clover(wcl_lattice* lat);
+/* Alternative to wcl_compute_clover: C given on the host as double[V][2][36],
+ * block k (k=0: spins 0,1; k=1: spins 2,3), index 3*(spin mod 2)+colour;
+ * 6 real diagonal entries, then the 15 complex strictly-upper entries
+ * (re, im) in row-major order.  Synchronous. */
+int wcl_upload_clover(wcl_lattice* lat, const double* C);
+/* Reads the resident FP64 clover back in the same packed host layout. */
+int wcl_download_clover(wcl_lattice* lat, double* C);
+
+/* ---- spinor fields ---- */
+
+/* Size in bytes of a device spinor buffer of nrhs fields at precision prec. */
+uint64_t wcl_spinor_bytes(const wcl_lattice* lat, int prec, int nrhs);
+/* host/device FP64 AoS -> device internal layout (and back).  The *_dev
+ * variants take a device pointer to the AoS data. */
+int wcl_pack_spinor(wcl_lattice* lat, int prec, int nrhs, const double* host_aos, void* dev_soa, void* stream);
+int wcl_unpack_spinor(wcl_lattice* lat, int prec, int nrhs, const void* dev_soa, double* host_aos, void* stream);
+int wcl_pack_spinor_dev(wcl_lattice* lat, int prec, int nrhs, const double* dev_aos, void* dev_soa, void* stream);
+int wcl_unpack_spinor_dev(wcl_lattice* lat, int prec, int nrhs, const void* dev_soa, double* dev_aos, void* stream);
+
+/* ---- operators ---- */
+
+/* out = D in for nrhs fields (Eq. (1)), periodic lattice with the bc phases,
+ * at storage precision prec for spinors, links and clover (arithmetic in
+ * FP64 for WCL_F64, FP32 otherwise).  in and out must not alias. */
+int wcl_apply_D(wcl_lattice* lat, int prec, double kappa, double csw, const void* in_dev, void* out_dev, int nrhs,
+                void* stream);
+
+/* Domain operator test surface (Sec. 2): for every domain i,
+ * out_i = D_{Omega'_i} P_{Omega'_i} in, D_{Omega'} being the principal
+ * submatrix of D on the site set Omega' (hops leaving it dropped).  in is an
+ * FP32 field (1 rhs); out_host receives double[nblocks][ext_volume][4][3][2],
+ * sites of each domain in lexicographic order of their local coordinates
+ * l_mu = x_mu - o_mu + s_mu (mod L_mu), o = domain origin.  Synchronous. */
+int wcl_apply_D_blocks(wcl_lattice* lat, const wcl_ras_params* ras, double kappa, double csw, const void* in_dev,
+                       double* out_host, void* stream);
+/* Number of domains and extended-domain volume for ras->block, ras->s. */
+int wcl_block_info(const wcl_lattice* lat, const wcl_ras_params* ras, int64_t* nblocks, int64_t* ext_volume);
+
+/* v = K_RAS r (Algorithm 1 / Eq. (2)) for nrhs FP32 fields; r and v are
+ * FP32 device buffers that must not alias. */
+int wcl_ras_precondition(wcl_lattice* lat, const wcl_ras_params* ras, double kappa, double csw, const void* r_dev,
+                         void* v_dev, int nrhs, void* stream);
+
+/* ---- solvers ---- */
+
+/* Mixed-precision nested BiCGStab (Sec. 3) for nrhs FP64 fields:
+ * eta_dev, phi_dev are FP64 device buffers (internal layout).  phi is
+ * overwritten (zero initial guess).  Blocks until done; stats may be NULL
+ * (with nrhs > 1 the stats are summed over the right-hand sides and
+ * true_resid is the largest).  Returns WCL_ENOTCONV with the best iterate in
+ * phi if tol_outer is not reached. */
+int wcl_solve_nested_bicgstab(wcl_lattice* lat, const wcl_solver_params* p, double kappa, double csw,
+                              const void* eta_dev, void* phi_dev, int nrhs, wcl_solve_stats* stats, void* stream);
+/* Plain unpreconditioned FP64 BiCGStab (the baseline): stops when the
+ * recursive residual is below tol*|eta| and reports the true residual. */
+int wcl_solve_bicgstab_f64(wcl_lattice* lat, double tol, int max_iter, double kappa, double csw, const void* eta_dev,
+                           void* phi_dev, wcl_solve_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WCL_H */

@@ -1,0 +1,415 @@
+// Device building blocks: storage loads/stores for the three precisions,
+// two-row link reconstruction, packed-Hermitian clover products, the
+// chiral-basis spin projections and the per-site Wilson-clover stencil.
+#pragma once
+
+#include "wcl_internal.h"
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f8v __attribute__((ext_vector_type(8)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+
+#define WCL_DEV __device__ __forceinline__
+
+template <int P>
+struct Real {
+    using T = float;
+};
+template <>
+struct Real<WCL_F64> {
+    using T = double;
+};
+
+// Non-temporal loads for data streamed exactly once per launch (links,
+// clover); neighbour-shared spinor data uses ordinary cached loads.
+template <typename V>
+WCL_DEV V ld_nt(const V* p) {
+    return __builtin_nontemporal_load(p);
+}
+template <typename V>
+WCL_DEV void st_nt(V* p, V v) {
+    __builtin_nontemporal_store(v, p);
+}
+
+// ------------------------------------------------------------ spinors ---
+// s[24]: component k = 3*spin + colour at s[2k] (re), s[2k+1] (im).
+template <int P>
+struct SpinorIO;
+
+template <>
+struct SpinorIO<WCL_F64> {
+    using T = double;
+    WCL_DEV static void load(const void* base, int V, int i, T s[24]) {
+        const d2v* p = (const d2v*)base;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            d2v v = p[(size_t)k * V + i];
+            s[2 * k] = v.x;
+            s[2 * k + 1] = v.y;
+        }
+    }
+    WCL_DEV static void store(void* base, int V, int i, const T s[24]) {
+        d2v* p = (d2v*)base;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            d2v v = {s[2 * k], s[2 * k + 1]};
+            st_nt(p + (size_t)k * V + i, v);
+        }
+    }
+};
+
+template <>
+struct SpinorIO<WCL_F32> {
+    using T = float;
+    WCL_DEV static void load(const void* base, int V, int i, T s[24]) {
+        const f4v* p = (const f4v*)base;
+#pragma unroll
+        for (int g = 0; g < 6; ++g) {
+            f4v v = p[(size_t)g * V + i];
+            s[4 * g] = v.x;
+            s[4 * g + 1] = v.y;
+            s[4 * g + 2] = v.z;
+            s[4 * g + 3] = v.w;
+        }
+    }
+    WCL_DEV static void store(void* base, int V, int i, const T s[24]) {
+        f4v* p = (f4v*)base;
+#pragma unroll
+        for (int g = 0; g < 6; ++g) {
+            f4v v = {s[4 * g], s[4 * g + 1], s[4 * g + 2], s[4 * g + 3]};
+            st_nt(p + (size_t)g * V + i, v);
+        }
+    }
+};
+
+// FP16 spinor: 24 binary16 values of value/scale plus an FP32 per-site
+// scale = max |component| (round-to-nearest-even conversion).
+template <>
+struct SpinorIO<WCL_F16> {
+    using T = float;
+    WCL_DEV static const float* scale_ptr(const void* base, int V) {
+        return (const float*)((const char*)base + round_up_dev(48 * (size_t)V, 256));
+    }
+    WCL_DEV static size_t round_up_dev(size_t n, size_t a) { return (n + a - 1) / a * a; }
+    WCL_DEV static void load(const void* base, int V, int i, T s[24]) {
+        const h8v* p = (const h8v*)base;
+        float sc = scale_ptr(base, V)[i];
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            f8v v = __builtin_convertvector(p[(size_t)g * V + i], f8v);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s[8 * g + j] = v[j] * sc;
+        }
+    }
+    WCL_DEV static void store(void* base, int V, int i, const T s[24]) {
+        float m = 0.f;
+#pragma unroll
+        for (int j = 0; j < 24; ++j) m = fmaxf(m, fabsf(s[j]));
+        float inv = m > 0.f ? 1.0f / m : 0.f;
+        h8v* p = (h8v*)base;
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            f8v v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = s[8 * g + j] * inv;
+            st_nt(p + (size_t)g * V + i, __builtin_convertvector(v, h8v));
+        }
+        st_nt((float*)scale_ptr(base, V) + i, m);
+    }
+};
+
+// ------------------------------------------------------------- links ----
+// u[18]: 3x3 complex, row-major, u[2*(3r+c)] = re.  Rows 0,1 are stored;
+// row 2 = conj(row0 x row1) (exact for SU(3)).
+template <typename T>
+WCL_DEV void reconstruct_row2(T u[18]) {
+#define RE(r, c) u[2 * (3 * (r) + (c))]
+#define IM(r, c) u[2 * (3 * (r) + (c)) + 1]
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int a = (c + 1) % 3, b = (c + 2) % 3;
+        // (row0_a row1_b - row0_b row1_a)^*
+        T re = RE(0, a) * RE(1, b) - IM(0, a) * IM(1, b) - (RE(0, b) * RE(1, a) - IM(0, b) * IM(1, a));
+        T im = RE(0, a) * IM(1, b) + IM(0, a) * RE(1, b) - (RE(0, b) * IM(1, a) + IM(0, b) * RE(1, a));
+        RE(2, c) = re;
+        IM(2, c) = -im;
+    }
+#undef RE
+#undef IM
+}
+
+template <int P>
+struct GaugeIO;
+
+template <>
+struct GaugeIO<WCL_F64> {
+    using T = double;
+    WCL_DEV static void load(const void* base, int V, int mu, int i, T u[18]) {
+        const d2v* p = (const d2v*)base + (size_t)mu * 6 * V;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            d2v v = ld_nt(p + (size_t)k * V + i);
+            u[2 * k] = v.x;
+            u[2 * k + 1] = v.y;
+        }
+        reconstruct_row2(u);
+    }
+};
+
+template <>
+struct GaugeIO<WCL_F32> {
+    using T = float;
+    WCL_DEV static void load(const void* base, int V, int mu, int i, T u[18]) {
+        const f4v* p = (const f4v*)base + (size_t)mu * 3 * V;
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            f4v v = ld_nt(p + (size_t)g * V + i);
+            u[4 * g] = v.x;
+            u[4 * g + 1] = v.y;
+            u[4 * g + 2] = v.z;
+            u[4 * g + 3] = v.w;
+        }
+        reconstruct_row2(u);
+    }
+};
+
+template <>
+struct GaugeIO<WCL_F16> {
+    using T = float;
+    WCL_DEV static void load(const void* base, int V, int mu, int i, T u[18]) {
+        const h4v* p = (const h4v*)base + (size_t)mu * 3 * V;
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            f4v v = __builtin_convertvector(ld_nt(p + (size_t)g * V + i), f4v);
+            u[4 * g] = v.x;
+            u[4 * g + 1] = v.y;
+            u[4 * g + 2] = v.z;
+            u[4 * g + 3] = v.w;
+        }
+        reconstruct_row2(u);
+    }
+};
+
+// ------------------------------------------------------------ clover ----
+// c[72]: blocks k = 0, 1 of 36 reals (6 diagonal reals, 15 complex upper
+// entries row-major (0,1),(0,2)..(0,5),(1,2)..(4,5)).
+template <int P>
+struct CloverIO;
+
+template <>
+struct CloverIO<WCL_F64> {
+    using T = double;
+    WCL_DEV static void load(const void* base, int V, int i, T c[72]) {
+        const d2v* p = (const d2v*)base;
+#pragma unroll
+        for (int k = 0; k < 36; ++k) {
+            d2v v = ld_nt(p + (size_t)k * V + i);
+            c[2 * k] = v.x;
+            c[2 * k + 1] = v.y;
+        }
+    }
+};
+
+template <>
+struct CloverIO<WCL_F32> {
+    using T = float;
+    WCL_DEV static void load(const void* base, int V, int i, T c[72]) {
+        const f4v* p = (const f4v*)base;
+#pragma unroll
+        for (int k = 0; k < 18; ++k) {
+            f4v v = ld_nt(p + (size_t)k * V + i);
+            c[4 * k] = v.x;
+            c[4 * k + 1] = v.y;
+            c[4 * k + 2] = v.z;
+            c[4 * k + 3] = v.w;
+        }
+    }
+};
+
+template <>
+struct CloverIO<WCL_F16> {
+    using T = float;
+    WCL_DEV static void load(const void* base, int V, int i, T c[72]) {
+        const h8v* p = (const h8v*)base;
+        const float* sc = (const float*)((const char*)base + (((size_t)V * 144 + 255) / 256) * 256);
+        float s = sc[i];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            f8v v = __builtin_convertvector(ld_nt(p + (size_t)k * V + i), f8v);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) c[8 * k + j] = v[j] * s;
+        }
+    }
+};
+
+// y = C_k x for one packed 6x6 Hermitian block (x, y: 6 complex).
+template <typename T>
+WCL_DEV void herm6_apply(const T* c, const T* x, T* y) {
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        y[2 * a] = c[a] * x[2 * a];
+        y[2 * a + 1] = c[a] * x[2 * a + 1];
+    }
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = a + 1; b < 6; ++b, ++k) {
+            T re = c[6 + 2 * k], im = c[6 + 2 * k + 1];
+            // y_a += c_ab x_b ; y_b += conj(c_ab) x_a
+            y[2 * a] += re * x[2 * b] - im * x[2 * b + 1];
+            y[2 * a + 1] += re * x[2 * b + 1] + im * x[2 * b];
+            y[2 * b] += re * x[2 * a] + im * x[2 * a + 1];
+            y[2 * b + 1] += re * x[2 * a + 1] - im * x[2 * a];
+        }
+}
+
+// ----------------------------------------------------- spin projection --
+// Chiral basis: gamma_k = [[0,-i s_k],[i s_k,0]], gamma_t = [[0,-1],[-1,0]].
+// With psi = (u0,u1,l0,l1) the rank-2 projections are
+//   (1 -+ gamma_mu) psi = (h0, h1, lower(h)),
+// and after the colour matrix acts on h the lower spins are rebuilt from it.
+// FWD = true: (1 - gamma_mu) (forward hop), false: (1 + gamma_mu).
+template <int MU, bool FWD, typename T>
+WCL_DEV void spin_project(const T s[24], T h[12]) {
+    const T* u0 = s;
+    const T* u1 = s + 6;
+    const T* l0 = s + 12;
+    const T* l1 = s + 18;
+    const T sg = FWD ? T(1) : T(-1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int r = 2 * c, i = 2 * c + 1;
+        if (MU == 0) {  // h0 = u0 +- i l1, h1 = u1 +- i l0
+            h[r] = u0[r] - sg * l1[i];
+            h[i] = u0[i] + sg * l1[r];
+            h[6 + r] = u1[r] - sg * l0[i];
+            h[6 + i] = u1[i] + sg * l0[r];
+        } else if (MU == 1) {  // h0 = u0 +- l1, h1 = u1 -+ l0
+            h[r] = u0[r] + sg * l1[r];
+            h[i] = u0[i] + sg * l1[i];
+            h[6 + r] = u1[r] - sg * l0[r];
+            h[6 + i] = u1[i] - sg * l0[i];
+        } else if (MU == 2) {  // h0 = u0 +- i l0, h1 = u1 -+ i l1
+            h[r] = u0[r] - sg * l0[i];
+            h[i] = u0[i] + sg * l0[r];
+            h[6 + r] = u1[r] + sg * l1[i];
+            h[6 + i] = u1[i] - sg * l1[r];
+        } else {  // h = u +- l
+            h[r] = u0[r] + sg * l0[r];
+            h[i] = u0[i] + sg * l0[i];
+            h[6 + r] = u1[r] + sg * l1[r];
+            h[6 + i] = u1[i] + sg * l1[i];
+        }
+    }
+}
+
+// acc += f * (w0, w1, lower(w)) for the projection spin_project<MU,FWD>.
+template <int MU, bool FWD, typename T>
+WCL_DEV void spin_accumulate(const T w[12], T f, T acc[24]) {
+    const T sg = FWD ? T(1) : T(-1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int r = 2 * c, i = 2 * c + 1;
+        const T w0r = w[r], w0i = w[i], w1r = w[6 + r], w1i = w[6 + i];
+        acc[r] += f * w0r;
+        acc[i] += f * w0i;
+        acc[6 + r] += f * w1r;
+        acc[6 + i] += f * w1i;
+        if (MU == 0) {  // lower = -+i (w1, w0)
+            acc[12 + r] += f * (sg * w1i);
+            acc[12 + i] += f * (-sg * w1r);
+            acc[18 + r] += f * (sg * w0i);
+            acc[18 + i] += f * (-sg * w0r);
+        } else if (MU == 1) {  // lower = -+(w1, -w0)
+            acc[12 + r] += f * (-sg * w1r);
+            acc[12 + i] += f * (-sg * w1i);
+            acc[18 + r] += f * (sg * w0r);
+            acc[18 + i] += f * (sg * w0i);
+        } else if (MU == 2) {  // lower = -+i (w0, -w1)
+            acc[12 + r] += f * (sg * w0i);
+            acc[12 + i] += f * (-sg * w0r);
+            acc[18 + r] += f * (-sg * w1i);
+            acc[18 + i] += f * (sg * w1r);
+        } else {  // lower = +-(w0, w1)
+            acc[12 + r] += f * (sg * w0r);
+            acc[12 + i] += f * (sg * w0i);
+            acc[18 + r] += f * (sg * w1r);
+            acc[18 + i] += f * (sg * w1i);
+        }
+    }
+}
+
+// w = U h (DAG = false) or U^dag h (DAG = true), h/w: 2 colour vectors.
+template <bool DAG, typename T>
+WCL_DEV void su3_apply2(const T u[18], const T h[12], T w[12]) {
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            T re = 0, im = 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const int ab = DAG ? 2 * (3 * b + a) : 2 * (3 * a + b);
+                const T ur = u[ab], ui = DAG ? -u[ab + 1] : u[ab + 1];
+                const T hr = h[6 * sp + 2 * b], hi = h[6 * sp + 2 * b + 1];
+                re += ur * hr - ui * hi;
+                im += ur * hi + ui * hr;
+            }
+            w[6 * sp + 2 * a] = re;
+            w[6 * sp + 2 * a + 1] = im;
+        }
+}
+
+// acc = s + csw*kappa * C s (the site-diagonal term A(x) s).
+template <typename T>
+WCL_DEV void clover_term(const T c[72], const T s[24], T ck, T acc[24]) {
+    T y[12];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        herm6_apply(c + 36 * k, s + 12 * k, y);
+#pragma unroll
+        for (int j = 0; j < 12; ++j) acc[12 * k + j] = s[12 * k + j] + ck * y[j];
+    }
+}
+
+// ------------------------------------------------------ XCD remapping ---
+// Workgroups are dispatched round-robin over the 8 XCDs; remap so that
+// each XCD walks a contiguous range of logical workgroup ids (and thereby a
+// contiguous piece of the column-ordered lattice in its own L2).
+WCL_DEV int xcd_remap(int b, int n) {
+    const int nx = 8;
+    int xcd = b % nx, k = b / nx;
+    int q = n / nx, r = n % nx;
+    return xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+}
+
+// --------------------------------------------------------- reductions ---
+WCL_DEV double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum of d[0..2] over the workgroup (up to 1024 threads) in a fixed order;
+// thread 0 writes the three sums to out.
+WCL_DEV void block_reduce3(double d[3], double* out) {
+    __shared__ double sh[16][3];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d[k] = wave_sum(d[k]);
+    if (l == 0)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sh[w][k] = d[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int k = 0; k < 3; ++k) {
+            double s = 0.0;
+            for (int q = 0; q < nw; ++q) s += sh[q][k];
+            out[k] = s;
+        }
+    }
+}

@@ -1,0 +1,164 @@
+// Internal definitions shared by the HIP sources of the library: error
+// handling, the device site layout, storage formats and small complex
+// helpers.  Not part of the public ABI (include/wcl.h).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "wcl.h"
+
+// ------------------------------------------------------------ errors ----
+void wcl_set_error(const char* fmt, ...);
+
+#define WCL_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            wcl_set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                          __LINE__);                                                       \
+            return WCL_EHIP;                                                               \
+        }                                                                                  \
+    } while (0)
+
+#define WCL_CHECK(expr)          \
+    do {                         \
+        int rc_ = (expr);        \
+        if (rc_ != WCL_OK) return rc_; \
+    } while (0)
+
+// ---------------------------------------------------------- geometry ----
+// Device site order.  The lattice is cut into columns of cross-section
+// cx*cy*cz (powers of two dividing Lx, Ly, Lz) that run the full t extent.
+// A site's internal index is
+//     col * Vc + t * S + (lx + cx*(ly + cy*lz)),   S = cx*cy*cz, Vc = S*Lt,
+// with col = Cx + nCx*(Cy + nCy*Cz) the column of (x,y,z).  A wavefront
+// streams along x inside one t-slice of one column, and consecutive
+// workgroups walk a column in t, so the +-t neighbours of a slice are read
+// while the previous slice is still in the XCD's L2.
+struct Geom {
+    int L[4];
+    int c[3];
+    int lc[3];
+    int nC[3];
+    int S;
+    int Vc;
+    int V;
+    int bc[4];
+};
+
+__host__ __device__ inline void geom_coords(const Geom& g, int i, int x[4]) {
+    int col = i / g.Vc;
+    int r = i - col * g.Vc;
+    int t = r / g.S;
+    int l = r - t * g.S;
+    int lx = l & (g.c[0] - 1);
+    int ly = (l >> g.lc[0]) & (g.c[1] - 1);
+    int lz = l >> (g.lc[0] + g.lc[1]);
+    int Cx = col % g.nC[0];
+    int q = col / g.nC[0];
+    int Cy = q % g.nC[1];
+    int Cz = q / g.nC[1];
+    x[0] = (Cx << g.lc[0]) + lx;
+    x[1] = (Cy << g.lc[1]) + ly;
+    x[2] = (Cz << g.lc[2]) + lz;
+    x[3] = t;
+}
+
+__host__ __device__ inline int geom_index(const Geom& g, const int x[4]) {
+    int col = (x[0] >> g.lc[0]) + g.nC[0] * ((x[1] >> g.lc[1]) + g.nC[1] * (x[2] >> g.lc[2]));
+    int l = (x[0] & (g.c[0] - 1)) + g.c[0] * ((x[1] & (g.c[1] - 1)) + g.c[1] * (x[2] & (g.c[2] - 1)));
+    return col * g.Vc + x[3] * g.S + l;
+}
+
+__host__ __device__ inline int canonical_index(const Geom& g, const int x[4]) {
+    return x[0] + g.L[0] * (x[1] + g.L[1] * (x[2] + g.L[2] * x[3]));
+}
+
+__host__ __device__ inline void canonical_coords(const Geom& g, int j, int x[4]) {
+    x[0] = j % g.L[0];
+    j /= g.L[0];
+    x[1] = j % g.L[1];
+    j /= g.L[1];
+    x[2] = j % g.L[2];
+    x[3] = j / g.L[2];
+}
+
+// ------------------------------------------------------ domain layout ---
+// Domains Omega_i tile the lattice by b from the origin; Omega'_i adds s_mu
+// sites per side (s_mu = 0 where b_mu = L_mu).  Extended domains are stored
+// one after the other, sites in lexicographic order of the local coordinate
+// l_mu in [0, e_mu), e_mu = b_mu + 2 s_mu; global x_mu = o_mu - s_mu + l_mu.
+struct Blocks {
+    int b[4];
+    int s[4];
+    int e[4];
+    int nb[4];
+    int nblocks;
+    int ev;  // extended volume
+    int n_ras, n_dominv;
+};
+
+// ------------------------------------------------------ storage -------
+// Spinor (per right-hand side; rhs stride = wcl_spinor_bytes(.., 1)):
+//   F64: double2[12][V]         component k = 3*spin + colour
+//   F32: float4 [6][V]          float4 g = components 2g, 2g+1 (re,im,re,im)
+//   F16: uint4  [3][V] + float[V] scale; uint4 g = reals 8g..8g+7 / scale
+// Gauge (two rows per link; row 2 = conj(row0 x row1) is rebuilt on load):
+//   F64: double2[4][6][V]   F32: float4[4][3][V]   F16: uint2[4][3][V]
+// Clover C (kappa-independent), 72 reals per site = blocks k=0,1 of 36:
+//   6 real diagonal entries then 15 complex upper entries, row-major:
+//   F64: double2[36][V]   F32: float4[18][V]   F16: uint4[9][V] + float[V] scale
+inline size_t round_up(size_t n, size_t a) { return (n + a - 1) / a * a; }
+
+inline size_t spinor_rhs_bytes(int prec, int64_t V) {
+    switch (prec) {
+        case WCL_F64: return round_up(192 * (size_t)V, 256);
+        case WCL_F32: return round_up(96 * (size_t)V, 256);
+        default: return round_up(48 * (size_t)V, 256) + round_up(4 * (size_t)V, 256);
+    }
+}
+inline size_t gauge_bytes(int prec, int64_t V) {
+    return (size_t)V * 4 * 12 * (prec == WCL_F64 ? 8 : prec == WCL_F32 ? 4 : 2);
+}
+inline size_t clover_bytes(int prec, int64_t V) {
+    return prec == WCL_F64 ? (size_t)V * 72 * 8
+           : prec == WCL_F32 ? (size_t)V * 72 * 4
+                             : round_up((size_t)V * 144, 256) + round_up((size_t)V * 4, 256);
+}
+// offset of the FP16 scale array inside an FP16 spinor (per rhs) / clover
+inline size_t half_spinor_scale_offset(int64_t V) { return round_up(48 * (size_t)V, 256); }
+inline size_t half_clover_scale_offset(int64_t V) { return round_up((size_t)V * 144, 256); }
+
+// ------------------------------------------------------ structures -----
+struct wcl_ctx {
+    int device;
+    uint64_t budget;
+    uint64_t in_use;
+    int arch_major;
+    int num_cu;
+};
+
+struct Workspace;  // solver scratch, defined in wcl_solver.hip
+
+struct wcl_lattice {
+    wcl_ctx* ctx;
+    Geom g;
+    int64_t V;
+    bool has_gauge = false, has_clover = false;
+    void* gauge[3] = {nullptr, nullptr, nullptr};   // indexed by WCL_F64/F32/F16
+    void* clover[3] = {nullptr, nullptr, nullptr};
+    Workspace* ws = nullptr;
+};
+
+// device memory accounting against the context budget
+int wcl_dev_alloc(wcl_ctx* ctx, void** p, size_t bytes);
+void wcl_dev_free(wcl_ctx* ctx, void* p, size_t bytes);
+
+int check_prec(int prec);
+void wcl_free_workspace(wcl_lattice* lat);  // solver workspace, wcl_solver.hip
+int make_blocks(const wcl_lattice* lat, const wcl_ras_params* p, Blocks* B);

@@ -1,0 +1,150 @@
+"""GPU parity of the field set-up and the full-lattice D application against
+the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from helpers import pack_clover_like_abi, rel_err
+from oracle import Oracle
+from paper_1011_3318_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-13, 1: 1e-5, 2: 5e-3}   # FP64, FP32, FP16 (relative L2)
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_1011_3318_amd import wcl
+    return wcl
+
+
+@pytest.fixture(scope="module")
+def ctx(W):
+    c = W.Context(0)
+    yield c
+    c.close()
+
+
+def make(W, ctx, dims, eps=0.5, seed=1, bc=(1, 1, 1, 1)):
+    U = I.random_gauge(dims, eps, seed)
+    lat = W.Lattice(ctx, dims, bc)
+    lat.upload_gauge(U)
+    return U, lat
+
+
+@pytest.mark.parametrize("dims,bc", [((4, 4, 4, 4), (1, 1, 1, 1)), ((6, 4, 10, 4), (1, 1, 1, -1)),
+                                     ((2, 2, 2, 2), (-1, 1, 1, -1))])
+def test_clover_build(W, ctx, dims, bc):
+    U, lat = make(W, ctx, dims, bc=bc)
+    dev = lat.download_clover()
+    ref = pack_clover_like_abi(Oracle(dims, U).clover())
+    assert np.abs(dev - ref).max() < 1e-14
+    lat.close()
+
+
+def test_clover_upload_roundtrip(W, ctx):
+    dims = (4, 4, 4, 4)
+    U, lat = make(W, ctx, dims)
+    ref = pack_clover_like_abi(Oracle(dims, U).clover())
+    lat.upload_clover(ref)
+    assert np.abs(lat.download_clover() - ref).max() == 0
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_pack_roundtrip(W, ctx, prec):
+    dims = (6, 4, 10, 4)
+    _, lat = make(W, ctx, dims)
+    psi = I.gaussian_source(dims, 3)
+    back = lat.unpack(lat.pack(psi, prec), prec)
+    assert rel_err(back, psi) <= {0: 0, 1: 1e-7, 2: 1e-3}[prec]
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("dims,bc", [((4, 4, 4, 4), (1, 1, 1, 1)), ((6, 4, 10, 4), (1, 1, 1, -1)),
+                                     ((2, 2, 2, 2), (1, -1, 1, -1)), ((8, 8, 8, 16), (1, 1, 1, -1))])
+def test_apply_D_parity(W, ctx, prec, dims, bc):
+    U, lat = make(W, ctx, dims, bc=bc)
+    kappa, csw = 0.124, 1.3
+    psi = I.gaussian_source(dims, 2)
+    x = lat.pack(psi, prec)
+    y = lat.empty(prec)
+    lat.apply_D(prec, kappa, csw, x, y)
+    got = lat.unpack(y, prec)
+    ref = Oracle(dims, U, bc=bc).apply_D(psi, kappa, csw)
+    assert rel_err(got, ref) <= TOL[prec]
+    if prec == 0:
+        assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_apply_D_multi_rhs_equals_single(W, ctx, prec):
+    dims = (8, 4, 4, 8)
+    U, lat = make(W, ctx, dims)
+    psi = I.gaussian_source(dims, 5, nrhs=3)
+    x = lat.pack(psi, prec, nrhs=3)
+    y = lat.empty(prec, 3)
+    lat.apply_D(prec, 0.12, 1.0, x, y, nrhs=3)
+    many = lat.unpack(y, prec, nrhs=3)
+    for r in range(3):
+        xs = lat.pack(psi[r], prec)
+        ys = lat.empty(prec)
+        lat.apply_D(prec, 0.12, 1.0, xs, ys)
+        assert np.array_equal(lat.unpack(ys, prec), many[r])
+    lat.close()
+
+
+def test_apply_D_deterministic(W, ctx):
+    dims = (8, 8, 8, 8)
+    _, lat = make(W, ctx, dims)
+    x = lat.pack(I.gaussian_source(dims, 2), 1)
+    y1, y2 = lat.empty(1), lat.empty(1)
+    lat.apply_D(1, 0.125, 1.0, x, y1)
+    lat.apply_D(1, 0.125, 1.0, x, y2)
+    import torch
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    lat.close()
+
+
+@pytest.fixture(scope="module")
+def big(W, ctx):
+    dims = (32, 32, 32, 32)
+    U, lat = make(W, ctx, dims, eps=1.0)
+    yield dims, U, lat
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_apply_D_32x4_sampled(W, big, prec):
+    """The benchmark's 32^4 shape: compare sampled sites one by one."""
+    dims, U, lat = big
+    psi = I.gaussian_source(dims, 2)
+    x = lat.pack(psi, prec)
+    y = lat.empty(prec)
+    lat.apply_D(prec, 0.125, 1.0, x, y)
+    got = lat.unpack(y, prec)
+    sites = np.random.default_rng(0).choice(I.volume(dims), 2000, replace=False)
+    # include lattice corners (all wrap-around hops)
+    sites = np.concatenate([sites, [0, I.volume(dims) - 1, 31, 32 * 32 * 32 * 31]])
+    ref = Oracle(dims, U, precompute_clover=False).apply_D_sites(psi, 0.125, 1.0, sites)
+    assert rel_err(got[sites], ref) <= TOL[prec]
+
+
+def test_input_validation(W, ctx):
+    dims = (4, 4, 4, 4)
+    lat = W.Lattice(ctx, dims)
+    x = lat.empty(1)
+    with pytest.raises(W.WclError) as e:
+        lat.apply_D(1, 0.1, 1.0, x, lat.empty(1))
+    assert e.value.code == W.ESTATE          # no gauge yet
+    U = I.random_gauge(dims, 0.5, 1)
+    U[3, 2, 0, 0] *= 1.01
+    with pytest.raises(W.WclError) as e:
+        lat.upload_gauge(U)
+    assert e.value.code == W.EUNITARITY
+    with pytest.raises(W.WclError):
+        W.Lattice(ctx, (4, 4, 1, 4))
+    lat.close()
