@@ -1,0 +1,346 @@
+// Vector kernels of the BiCGStab solvers (FP64 outer, FP32 inner), batched
+// over right-hand sides.  The solver scalars live on the device (struct
+// Scal per rhs) so that no kernel waits for the host; every reduction writes
+// per-workgroup partial sums which a finalize kernel adds in a fixed order
+// (results are bitwise reproducible run to run).
+#include "wcl_device.h"
+#include "wcl_kernels.h"
+
+template <int P>
+struct Vec;
+template <>
+struct Vec<WCL_F64> {
+    using E = d2v;   // one complex number per element
+    static constexpr int per_site = 12;
+};
+template <>
+struct Vec<WCL_F32> {
+    using E = f4v;   // two complex numbers per element
+    static constexpr int per_site = 6;
+};
+
+WCL_DEV void cdiv(double ar, double ai, double br, double bi, double& cr, double& ci) {
+    double d = br * br + bi * bi;
+    cr = (ar * br + ai * bi) / d;
+    ci = (ai * br - ar * bi) / d;
+}
+WCL_DEV void cmul(double ar, double ai, double br, double bi, double& cr, double& ci) {
+    cr = ar * br - ai * bi;
+    ci = ar * bi + ai * br;
+}
+
+// complex scalar * element helpers
+WCL_DEV f4v cm(double cr, double ci, f4v a) {
+    float r = (float)cr, i = (float)ci;
+    return f4v{r * a.x - i * a.y, r * a.y + i * a.x, r * a.z - i * a.w, r * a.w + i * a.z};
+}
+WCL_DEV d2v cm(double cr, double ci, d2v a) {
+    return d2v{cr * a.x - ci * a.y, cr * a.y + ci * a.x};
+}
+
+// <a, b> contributions (re, im) and |b|^2
+WCL_DEV void dot_acc(d2v a, d2v b, double d[3]) {
+    d[0] += a.x * b.x + a.y * b.y;
+    d[1] += a.x * b.y - a.y * b.x;
+    d[2] += b.x * b.x + b.y * b.y;
+}
+WCL_DEV void dot_acc(f4v a, f4v b, double d[3]) {
+    float re = a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+    float im = a.x * b.y - a.y * b.x + a.z * b.w - a.w * b.z;
+    float nn = b.x * b.x + b.y * b.y + b.z * b.z + b.w * b.w;
+    d[0] += re;
+    d[1] += im;
+    d[2] += nn;
+}
+
+struct BlasGrid {
+    int n;        // elements per rhs
+    int stride;   // elements between rhs
+    int G;        // workgroups per rhs
+};
+
+#define BLAS_PROLOGUE                                   \
+    const int rhs = blockIdx.x / bg.G;                  \
+    const int wg = blockIdx.x % bg.G;                   \
+    const size_t base = (size_t)rhs * bg.stride;        \
+    const int step = bg.G * 256;
+
+// p = r + beta (p - omega v), beta = (rho/rho_old)(alpha/omega); partial |p|^2
+template <int P>
+__global__ __launch_bounds__(256) void k_p_update(BlasGrid bg, const Scal* sc, const void* r_, void* p_,
+                                                   const void* v_, double* partial) {
+    using E = typename Vec<P>::E;
+    BLAS_PROLOGUE
+    const Scal& S = sc[rhs];
+    double d[3] = {0, 0, 0};
+    if (S.active) {
+        double t1r, t1i, t2r, t2i, br, bi;
+        cdiv(S.rho[0], S.rho[1], S.rho_old[0], S.rho_old[1], t1r, t1i);
+        cdiv(S.alpha[0], S.alpha[1], S.omega[0], S.omega[1], t2r, t2i);
+        cmul(t1r, t1i, t2r, t2i, br, bi);
+        const double wr = S.omega[0], wi = S.omega[1];
+        const E* r = (const E*)r_ + base;
+        E* p = (E*)p_ + base;
+        const E* v = (const E*)v_ + base;
+        for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step) {
+            E pv = p[k] - cm(wr, wi, v[k]);
+            E np = r[k] + cm(br, bi, pv);
+            p[k] = np;
+            dot_acc(np, np, d);
+        }
+    }
+    block_reduce3(d, partial + 3 * ((size_t)rhs * bg.G + wg));
+}
+
+// s = r - alpha v
+template <int P>
+__global__ __launch_bounds__(256) void k_s_update(BlasGrid bg, const Scal* sc, const void* r_, const void* v_,
+                                                   void* s_) {
+    using E = typename Vec<P>::E;
+    BLAS_PROLOGUE
+    const Scal& S = sc[rhs];
+    if (!S.active) return;
+    const double ar = S.alpha[0], ai = S.alpha[1];
+    const E* r = (const E*)r_ + base;
+    const E* v = (const E*)v_ + base;
+    E* s = (E*)s_ + base;
+    for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step) s[k] = r[k] - cm(ar, ai, v[k]);
+}
+
+// x += alpha p^ + omega s^;  r = s - omega t;  partials <rhat, r>, |r|^2
+template <int P>
+__global__ __launch_bounds__(256) void k_xr_update(BlasGrid bg, const Scal* sc, void* x_, const void* ph_,
+                                                    const void* sh_, const void* s_, const void* t_, void* r_,
+                                                    const void* rh_, double* partial) {
+    using E = typename Vec<P>::E;
+    BLAS_PROLOGUE
+    const Scal& S = sc[rhs];
+    double d[3] = {0, 0, 0};
+    if (S.active) {
+        const double ar = S.alpha[0], ai = S.alpha[1], wr = S.omega[0], wi = S.omega[1];
+        E* x = (E*)x_ + base;
+        const E* ph = (const E*)ph_ + base;
+        const E* sh = (const E*)sh_ + base;
+        const E* s = (const E*)s_ + base;
+        const E* t = (const E*)t_ + base;
+        E* r = (E*)r_ + base;
+        const E* rh = (const E*)rh_ + base;
+        for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step) {
+            x[k] = x[k] + cm(ar, ai, ph[k]) + cm(wr, wi, sh[k]);
+            E nr = s[k] - cm(wr, wi, t[k]);
+            r[k] = nr;
+            dot_acc(rh[k], nr, d);
+        }
+    }
+    block_reduce3(d, partial + 3 * ((size_t)rhs * bg.G + wg));
+}
+
+// partials of <a, b> and |b|^2 (only for active rhs)
+template <int P>
+__global__ __launch_bounds__(256) void k_dot(BlasGrid bg, const Scal* sc, const void* a_, const void* b_,
+                                              double* partial) {
+    using E = typename Vec<P>::E;
+    BLAS_PROLOGUE
+    double d[3] = {0, 0, 0};
+    if (!sc || sc[rhs].active) {
+        const E* a = (const E*)a_ + base;
+        const E* b = (const E*)b_ + base;
+        for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step) dot_acc(a[k], b[k], d);
+    }
+    block_reduce3(d, partial + 3 * ((size_t)rhs * bg.G + wg));
+}
+
+// y = a (copy), or y = 0 when a == nullptr (a fill kernel, not a memset)
+template <int P>
+__global__ __launch_bounds__(256) void k_copy(BlasGrid bg, const void* a_, void* y_) {
+    using E = typename Vec<P>::E;
+    BLAS_PROLOGUE
+    E* y = (E*)y_ + base;
+    if (a_) {
+        const E* a = (const E*)a_ + base;
+        for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step) y[k] = a[k];
+    } else {
+        for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step) y[k] = E{};
+    }
+}
+
+// FP64 -> FP32 with factor 1/sqrt(S.pp) (inner right-hand side b = p/|p|);
+// FP32 -> FP64 with factor sqrt(S.pp) (p^ = |p| y).  One thread per FP32
+// element: float4 g of site i holds FP64 components 2g and 2g+1.
+__global__ __launch_bounds__(256) void k_to_f32_scaled(int V, int G, const Scal* sc, const void* a_, size_t astride2,
+                                                        void* y_, size_t ystride4) {
+    const int rhs = blockIdx.x / G, wg = blockIdx.x % G;
+    if (!sc[rhs].active) return;
+    const double f = sc[rhs].pp > 0 ? 1.0 / sqrt(sc[rhs].pp) : 0.0;
+    const d2v* a = (const d2v*)a_ + (size_t)rhs * astride2;
+    f4v* y = (f4v*)y_ + (size_t)rhs * ystride4;
+    const int n = 6 * V;
+    for (int k = wg * 256 + threadIdx.x; k < n; k += G * 256) {
+        const int g = k / V, i = k - g * V;
+        d2v u = a[(size_t)(2 * g) * V + i], w = a[(size_t)(2 * g + 1) * V + i];
+        y[k] = f4v{(float)(u.x * f), (float)(u.y * f), (float)(w.x * f), (float)(w.y * f)};
+    }
+}
+
+__global__ __launch_bounds__(256) void k_to_f64_scaled(int V, int G, const Scal* sc, const void* a_, size_t astride4,
+                                                        void* y_, size_t ystride2) {
+    const int rhs = blockIdx.x / G, wg = blockIdx.x % G;
+    if (!sc[rhs].active) return;
+    const double f = sqrt(sc[rhs].pp);
+    const f4v* a = (const f4v*)a_ + (size_t)rhs * astride4;
+    d2v* y = (d2v*)y_ + (size_t)rhs * ystride2;
+    const int n = 6 * V;
+    for (int k = wg * 256 + threadIdx.x; k < n; k += G * 256) {
+        const int g = k / V, i = k - g * V;
+        f4v v = a[k];
+        y[(size_t)(2 * g) * V + i] = d2v{(double)v.x * f, (double)v.y * f};
+        y[(size_t)(2 * g + 1) * V + i] = d2v{(double)v.z * f, (double)v.w * f};
+    }
+}
+
+// ----------------------------------------------------------- finalize ---
+// One workgroup per rhs adds the G partial triples in a fixed order and
+// applies the scalar step of BiCGStab selected by `kind`.
+__global__ __launch_bounds__(256) void k_finalize(const double* partial, int G, Scal* sc, int kind) {
+    const int rhs = blockIdx.x;
+    Scal& S = sc[rhs];
+    double d[3] = {0, 0, 0};
+    for (int k = threadIdx.x; k < G; k += 256) {
+        const double* q = partial + 3 * ((size_t)rhs * G + k);
+        d[0] += q[0];
+        d[1] += q[1];
+        d[2] += q[2];
+    }
+    __shared__ double tot[3];
+    block_reduce3(d, tot);
+    __syncthreads();
+    if (threadIdx.x != 0 || !S.active) return;
+    const double s0 = tot[0], s1 = tot[1], s2 = tot[2];
+    switch (kind) {
+        case FIN_ALPHA: {  // alpha = rho / <rhat, v>
+            S.rv[0] = s0;
+            S.rv[1] = s1;
+            if (s0 == 0.0 && s1 == 0.0) {
+                S.alpha[0] = S.alpha[1] = 0.0;
+                S.breakdown = 1;
+            } else {
+                cdiv(S.rho[0], S.rho[1], s0, s1, S.alpha[0], S.alpha[1]);
+            }
+            break;
+        }
+        case FIN_OMEGA: {  // omega = <t, s> / <t, t>; partial was <s, t>
+            S.tt = s2;
+            if (s2 > 0.0) {
+                S.omega[0] = s0 / s2;
+                S.omega[1] = -s1 / s2;
+            } else {
+                S.omega[0] = S.omega[1] = 0.0;
+            }
+            break;
+        }
+        case FIN_RHO: {  // rho_old = rho; rho = <rhat, r>; rr = |r|^2
+            S.rho_old[0] = S.rho[0];
+            S.rho_old[1] = S.rho[1];
+            S.rho[0] = s0;
+            S.rho[1] = s1;
+            S.rr = s2;
+            break;
+        }
+        case FIN_PP: S.pp = s2; break;
+        case FIN_RR: S.rr = s2; break;
+        case FIN_RR0: S.rr0 = s2; S.rr = s2; break;
+    }
+}
+
+// ------------------------------------------------------------ launchers --
+static BlasGrid blas_grid(int prec, int64_t V) {
+    BlasGrid bg;
+    bg.n = (int)(V * (prec == WCL_F64 ? 12 : 6));
+    bg.stride = (int)(spinor_rhs_bytes(prec, V) / 16);
+    bg.G = (int)std::min<int64_t>((bg.n + 255) / 256, 1024);
+    return bg;
+}
+
+int blas_partials(int prec, int64_t V) { return blas_grid(prec, V).G; }
+
+#define DISPATCH_P(prec, KERNEL, ...)                                                       \
+    do {                                                                                    \
+        BlasGrid bg = blas_grid(prec, V);                                                   \
+        if (prec == WCL_F64)                                                                \
+            KERNEL<WCL_F64><<<bg.G * nrhs, 256, 0, st>>>(bg, __VA_ARGS__);                  \
+        else                                                                                \
+            KERNEL<WCL_F32><<<bg.G * nrhs, 256, 0, st>>>(bg, __VA_ARGS__);                  \
+        WCL_HIP(hipGetLastError());                                                         \
+    } while (0)
+
+int blas_p_update(int prec, int64_t V, int nrhs, const Scal* sc, const void* r, void* p, const void* v,
+                  double* partial, hipStream_t st) {
+    DISPATCH_P(prec, k_p_update, sc, r, p, v, partial);
+    return WCL_OK;
+}
+int blas_s_update(int prec, int64_t V, int nrhs, const Scal* sc, const void* r, const void* v, void* s,
+                  hipStream_t st) {
+    DISPATCH_P(prec, k_s_update, sc, r, v, s);
+    return WCL_OK;
+}
+int blas_xr_update(int prec, int64_t V, int nrhs, const Scal* sc, void* x, const void* ph, const void* sh,
+                   const void* s, const void* t, void* r, const void* rh, double* partial, hipStream_t st) {
+    DISPATCH_P(prec, k_xr_update, sc, x, ph, sh, s, t, r, rh, partial);
+    return WCL_OK;
+}
+int blas_dot(int prec, int64_t V, int nrhs, const Scal* sc, const void* a, const void* b, double* partial,
+             hipStream_t st) {
+    DISPATCH_P(prec, k_dot, sc, a, b, partial);
+    return WCL_OK;
+}
+int blas_copy(int prec, int64_t V, int nrhs, const void* a, void* y, hipStream_t st) {
+    DISPATCH_P(prec, k_copy, a, y);
+    return WCL_OK;
+}
+int blas_to_f32_scaled(int64_t V, int nrhs, const Scal* sc, const void* a64, void* y32, hipStream_t st) {
+    BlasGrid bg = blas_grid(WCL_F32, V);
+    k_to_f32_scaled<<<bg.G * nrhs, 256, 0, st>>>((int)V, bg.G, sc, a64, spinor_rhs_bytes(WCL_F64, V) / 16, y32,
+                                                 spinor_rhs_bytes(WCL_F32, V) / 16);
+    WCL_HIP(hipGetLastError());
+    return WCL_OK;
+}
+int blas_to_f64_scaled(int64_t V, int nrhs, const Scal* sc, const void* a32, void* y64, hipStream_t st) {
+    BlasGrid bg = blas_grid(WCL_F32, V);
+    k_to_f64_scaled<<<bg.G * nrhs, 256, 0, st>>>((int)V, bg.G, sc, a32, spinor_rhs_bytes(WCL_F32, V) / 16, y64,
+                                                 spinor_rhs_bytes(WCL_F64, V) / 16);
+    WCL_HIP(hipGetLastError());
+    return WCL_OK;
+}
+int blas_finalize(const double* partial, int G, int nrhs, Scal* sc, int kind, hipStream_t st) {
+    k_finalize<<<nrhs, 256, 0, st>>>(partial, G, sc, kind);
+    WCL_HIP(hipGetLastError());
+    return WCL_OK;
+}
+
+// Restart of the rhs flagged with breakdown == 2: r = src (if given),
+// rhat = r, p = v = 0.
+template <int P>
+__global__ __launch_bounds__(256) void k_restart(BlasGrid bg, const Scal* sc, const void* src_, void* r_, void* rh_,
+                                                  void* p_, void* v_) {
+    using E = typename Vec<P>::E;
+    BLAS_PROLOGUE
+    if (sc[rhs].breakdown != 2) return;
+    E* r = (E*)r_ + base;
+    E* rh = (E*)rh_ + base;
+    E* p = (E*)p_ + base;
+    E* v = (E*)v_ + base;
+    const E* src = src_ ? (const E*)src_ + base : nullptr;
+    for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step) {
+        E rv = src ? src[k] : r[k];
+        r[k] = rv;
+        rh[k] = rv;
+        p[k] = E{};
+        v[k] = E{};
+    }
+}
+
+int blas_restart(int prec, int64_t V, int nrhs, const Scal* sc, const void* src, void* r, void* rh, void* p, void* v,
+                 hipStream_t st) {
+    DISPATCH_P(prec, k_restart, sc, src, r, rh, p, v);
+    return WCL_OK;
+}

@@ -1,0 +1,266 @@
+// RAS domain solves (Sec. 2, Algorithm 1): projection P_{Omega'_i}, the
+// Dirichlet domain operator D_{Omega'_i}, minimal-residual steps and the
+// restriction R_{Omega_i}, for all domains and right-hand sides at once.
+//
+// Split path: the extended domains are stored one after another in an FP32
+// workspace (float4 [6][NE] per rhs, NE = nblocks * ev).  Each workgroup
+// covers 256 sites of one domain, so a domain can span several workgroups;
+// every MR step is one launch of the domain operator (with per-workgroup
+// partial sums of <q, rho>, <q, q>) followed by one update launch that adds
+// the domain's partials in a fixed order.
+#include "wcl_device.h"
+#include "wcl_kernels.h"
+
+// local coordinates of extended-domain site l, and its global coordinates
+WCL_DEV void block_site(const Geom& g, const Blocks& B, int blk, int l, int lc[4], int x[4]) {
+    int t = l, tb = blk;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        lc[mu] = t % B.e[mu];
+        t /= B.e[mu];
+        int bc = tb % B.nb[mu];
+        tb /= B.nb[mu];
+        int v = bc * B.b[mu] - B.s[mu] + lc[mu];
+        x[mu] = v < 0 ? v + g.L[mu] : (v >= g.L[mu] ? v - g.L[mu] : v);
+    }
+}
+
+WCL_DEV int local_index(const Blocks& B, const int lc[4]) {
+    return lc[0] + B.e[0] * (lc[1] + B.e[1] * (lc[2] + B.e[2] * lc[3]));
+}
+
+WCL_DEV bool block_owned(const Blocks& B, const int lc[4]) {
+    bool o = true;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) o = o && lc[mu] >= B.s[mu] && lc[mu] < B.s[mu] + B.b[mu];
+    return o;
+}
+
+// projection: rho = P r on every extended site, x = 0
+template <int SRC>
+__global__ __launch_bounds__(256) void k_blk_project(BlockArgs a) {
+    const int per_rhs = a.B.nblocks * a.wpb;
+    const int rhs = blockIdx.x / per_rhs;
+    const int blk = (blockIdx.x % per_rhs) / a.wpb;
+    const int l = (blockIdx.x % a.wpb) * 256 + threadIdx.x;
+    if (l >= a.B.ev) return;
+    int lc[4], x[4];
+    block_site(a.g, a.B, blk, l, lc, x);
+    float s[24];
+    SpinorIO<SRC>::load((const char*)a.src + rhs * a.src_stride, a.g.V, geom_index(a.g, x), s);
+    const int e = blk * a.B.ev + l;
+    f4v* rho = (f4v*)a.rho + rhs * a.ws_stride;
+    f4v* xs = (f4v*)a.x + rhs * a.ws_stride;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        rho[(size_t)q * a.NE + e] = f4v{s[4 * q], s[4 * q + 1], s[4 * q + 2], s[4 * q + 3]};
+        xs[(size_t)q * a.NE + e] = f4v{0.f, 0.f, 0.f, 0.f};
+    }
+}
+
+WCL_DEV void ws_load(const f4v* base, int NE, int e, float s[24]) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        f4v v = base[(size_t)q * NE + e];
+        s[4 * q] = v.x;
+        s[4 * q + 1] = v.y;
+        s[4 * q + 2] = v.z;
+        s[4 * q + 3] = v.w;
+    }
+}
+WCL_DEV void ws_store(f4v* base, int NE, int e, const float s[24]) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) base[(size_t)q * NE + e] = f4v{s[4 * q], s[4 * q + 1], s[4 * q + 2], s[4 * q + 3]};
+}
+
+template <int MU, int GP>
+WCL_DEV void blk_hops(const BlockArgs& a, const f4v* rho, int blk, const int lc[4], const int x[4], int gi,
+                      float mk, float acc[24]) {
+    float s[24], h[12], w[12], u[18];
+    // forward neighbour: (1 - gamma_mu) U_mu(x) rho(x + mu)
+    {
+        int ln[4] = {lc[0], lc[1], lc[2], lc[3]};
+        bool in = true;
+        ln[MU] += 1;
+        if (ln[MU] == a.B.e[MU]) {
+            if (a.B.e[MU] == a.g.L[MU]) ln[MU] = 0;
+            else in = false;
+        }
+        if (in) {
+            float ph = (x[MU] == a.g.L[MU] - 1) ? (float)a.g.bc[MU] : 1.f;
+            ws_load(rho, a.NE, blk * a.B.ev + local_index(a.B, ln), s);
+            spin_project<MU, true>(s, h);
+            GaugeIO<GP>::load(a.gauge, a.g.V, MU, gi, u);
+            su3_apply2<false>(u, h, w);
+            spin_accumulate<MU, true>(w, mk * ph, acc);
+        }
+    }
+    // backward neighbour: (1 + gamma_mu) U_mu(x - mu)^dag rho(x - mu)
+    {
+        int ln[4] = {lc[0], lc[1], lc[2], lc[3]};
+        bool in = true;
+        ln[MU] -= 1;
+        if (ln[MU] < 0) {
+            if (a.B.e[MU] == a.g.L[MU]) ln[MU] = a.B.e[MU] - 1;
+            else in = false;
+        }
+        if (in) {
+            float ph = (x[MU] == 0) ? (float)a.g.bc[MU] : 1.f;
+            int y[4] = {x[0], x[1], x[2], x[3]};
+            y[MU] = x[MU] == 0 ? a.g.L[MU] - 1 : x[MU] - 1;
+            ws_load(rho, a.NE, blk * a.B.ev + local_index(a.B, ln), s);
+            spin_project<MU, false>(s, h);
+            GaugeIO<GP>::load(a.gauge, a.g.V, MU, geom_index(a.g, y), u);
+            su3_apply2<true>(u, h, w);
+            spin_accumulate<MU, false>(w, mk * ph, acc);
+        }
+    }
+}
+
+// q = D_{Omega'} rho on all extended sites; partials <q, rho>, <q, q> per workgroup
+template <int GP>
+__global__ __launch_bounds__(256) void k_blk_dslash(BlockArgs a) {
+    const int per_rhs = a.B.nblocks * a.wpb;
+    const int rhs = blockIdx.x / per_rhs;
+    const int blk = (blockIdx.x % per_rhs) / a.wpb;
+    const int wl = blockIdx.x % a.wpb;
+    const int l = wl * 256 + threadIdx.x;
+    double d[3] = {0, 0, 0};
+    if (l < a.B.ev) {
+        int lc[4], x[4];
+        block_site(a.g, a.B, blk, l, lc, x);
+        const int gi = geom_index(a.g, x);
+        const int e = blk * a.B.ev + l;
+        const f4v* rho = (const f4v*)a.rho + rhs * a.ws_stride;
+        float r0[24], acc[24];
+        ws_load(rho, a.NE, e, r0);
+        {
+            float c[72];
+            CloverIO<GP>::load(a.clover, a.g.V, gi, c);
+            clover_term(c, r0, (float)(a.csw * a.kappa), acc);
+        }
+        const float mk = (float)(-a.kappa);
+        blk_hops<0, GP>(a, rho, blk, lc, x, gi, mk, acc);
+        blk_hops<1, GP>(a, rho, blk, lc, x, gi, mk, acc);
+        blk_hops<2, GP>(a, rho, blk, lc, x, gi, mk, acc);
+        blk_hops<3, GP>(a, rho, blk, lc, x, gi, mk, acc);
+        ws_store((f4v*)a.q + rhs * a.ws_stride, a.NE, e, acc);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            float qr = acc[2 * k], qi = acc[2 * k + 1], rr = r0[2 * k], ri = r0[2 * k + 1];
+            d[0] += (double)(qr * rr + qi * ri);   // <q, rho>
+            d[1] += (double)(qr * ri - qi * rr);
+            d[2] += (double)(qr * qr + qi * qi);   // <q, q>
+        }
+    }
+    block_reduce3(d, a.partial + 3 * (((size_t)rhs * a.B.nblocks + blk) * a.wpb + wl));
+}
+
+// alpha = <q,rho>/<q,q> for the domain; x += alpha rho; rho -= alpha q.
+// On the last step the owned sites are written out (restriction):
+//   out (FP32) = x, or out += x when accumulating over sweeps,
+//   vj (storage precision) = x when requested.
+template <int VP>
+__global__ __launch_bounds__(256) void k_blk_update(BlockArgs a, int last) {
+    const int per_rhs = a.B.nblocks * a.wpb;
+    const int rhs = blockIdx.x / per_rhs;
+    const int blk = (blockIdx.x % per_rhs) / a.wpb;
+    const int l = (blockIdx.x % a.wpb) * 256 + threadIdx.x;
+    __shared__ float al[2];
+    if (threadIdx.x == 0) {
+        const double* p = a.partial + 3 * ((size_t)rhs * a.B.nblocks + blk) * a.wpb;
+        double s0 = 0, s1 = 0, s2 = 0;
+        for (int k = 0; k < a.wpb; ++k) {
+            s0 += p[3 * k];
+            s1 += p[3 * k + 1];
+            s2 += p[3 * k + 2];
+        }
+        al[0] = s2 > 0 ? (float)(s0 / s2) : 0.f;
+        al[1] = s2 > 0 ? (float)(s1 / s2) : 0.f;
+    }
+    __syncthreads();
+    if (l >= a.B.ev) return;
+    const float ar = al[0], ai = al[1];
+    const int e = blk * a.B.ev + l;
+    f4v* rho = (f4v*)a.rho + rhs * a.ws_stride;
+    f4v* q = (f4v*)a.q + rhs * a.ws_stride;
+    f4v* xs = (f4v*)a.x + rhs * a.ws_stride;
+    float xv[24];
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+        const size_t k = (size_t)g * a.NE + e;
+        f4v r = rho[k], qq = q[k], xx = xs[k];
+        xx = xx + f4v{ar * r.x - ai * r.y, ar * r.y + ai * r.x, ar * r.z - ai * r.w, ar * r.w + ai * r.z};
+        if (!last) {
+            r = r - f4v{ar * qq.x - ai * qq.y, ar * qq.y + ai * qq.x, ar * qq.z - ai * qq.w, ar * qq.w + ai * qq.z};
+            rho[k] = r;
+            xs[k] = xx;
+        }
+        xv[4 * g] = xx.x;
+        xv[4 * g + 1] = xx.y;
+        xv[4 * g + 2] = xx.z;
+        xv[4 * g + 3] = xx.w;
+    }
+    if (!last) return;
+    int lc[4], x[4];
+    block_site(a.g, a.B, blk, l, lc, x);
+    if (!block_owned(a.B, lc)) return;
+    const int gi = geom_index(a.g, x);
+    char* out = (char*)a.out + rhs * a.out_stride;
+    if (a.accumulate) {
+        float o[24];
+        SpinorIO<WCL_F32>::load(out, a.g.V, gi, o);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) o[k] += xv[k];
+        SpinorIO<WCL_F32>::store(out, a.g.V, gi, o);
+    } else {
+        SpinorIO<WCL_F32>::store(out, a.g.V, gi, xv);
+    }
+    if (a.vj) SpinorIO<VP>::store((char*)a.vj + rhs * a.vj_stride, a.g.V, gi, xv);
+}
+
+// Unpacks the extended-domain workspace q to FP64 AoS (test surface).
+__global__ __launch_bounds__(256) void k_blk_unpack(BlockArgs a, const float* ws, double* out) {
+    int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= a.NE) return;
+    float s[24];
+    ws_load((const f4v*)ws, a.NE, e, s);
+    for (int k = 0; k < 24; ++k) out[(size_t)e * 24 + k] = s[k];
+}
+
+static dim3 blk_grid(const BlockArgs& a) { return dim3((unsigned)(a.B.nblocks * a.wpb * a.nrhs)); }
+
+int launch_blk_project(const BlockArgs& a, int src_prec, hipStream_t st) {
+    if (src_prec == WCL_F32) k_blk_project<WCL_F32><<<blk_grid(a), 256, 0, st>>>(a);
+    else if (src_prec == WCL_F16) k_blk_project<WCL_F16><<<blk_grid(a), 256, 0, st>>>(a);
+    else {
+        wcl_set_error("domain projection: unsupported source precision");
+        return WCL_EINVAL;
+    }
+    WCL_HIP(hipGetLastError());
+    return WCL_OK;
+}
+
+int launch_blk_dslash(const BlockArgs& a, int gp, hipStream_t st) {
+    if (gp == WCL_F32) k_blk_dslash<WCL_F32><<<blk_grid(a), 256, 0, st>>>(a);
+    else if (gp == WCL_F16) k_blk_dslash<WCL_F16><<<blk_grid(a), 256, 0, st>>>(a);
+    else {
+        wcl_set_error("domain operator: unsupported storage precision");
+        return WCL_EINVAL;
+    }
+    WCL_HIP(hipGetLastError());
+    return WCL_OK;
+}
+
+int launch_blk_update(const BlockArgs& a, int vj_prec, int last, hipStream_t st) {
+    if (vj_prec == WCL_F16) k_blk_update<WCL_F16><<<blk_grid(a), 256, 0, st>>>(a, last);
+    else k_blk_update<WCL_F32><<<blk_grid(a), 256, 0, st>>>(a, last);
+    WCL_HIP(hipGetLastError());
+    return WCL_OK;
+}
+
+int launch_blk_unpack(const BlockArgs& a, const float* ws, double* out, hipStream_t st) {
+    k_blk_unpack<<<(a.NE + 255) / 256, 256, 0, st>>>(a, ws, out);
+    WCL_HIP(hipGetLastError());
+    return WCL_OK;
+}

@@ -30,3 +30,57 @@ int launch_unpack_clover(const Geom& g, const void* c64, double* host_dev, hipSt
 
 int dslash_partials_per_rhs(int V);
 int launch_dslash(const DslashArgs& a, int gp, int spi, int spo, int epi, int spy, hipStream_t st);
+
+// ------------------------------------------------------------- solvers --
+// BiCGStab scalars of one right-hand side, resident on the device.
+struct Scal {
+    double rho[2], rho_old[2], alpha[2], omega[2], rv[2];
+    double tt, rr, rr0, pp;
+    int active, breakdown;
+};
+enum { FIN_ALPHA = 0, FIN_OMEGA = 1, FIN_RHO = 2, FIN_PP = 3, FIN_RR = 4, FIN_RR0 = 5 };
+
+int blas_partials(int prec, int64_t V);
+int blas_p_update(int prec, int64_t V, int nrhs, const Scal* sc, const void* r, void* p, const void* v,
+                  double* partial, hipStream_t st);
+int blas_s_update(int prec, int64_t V, int nrhs, const Scal* sc, const void* r, const void* v, void* s,
+                  hipStream_t st);
+int blas_xr_update(int prec, int64_t V, int nrhs, const Scal* sc, void* x, const void* ph, const void* sh,
+                   const void* s, const void* t, void* r, const void* rh, double* partial, hipStream_t st);
+int blas_dot(int prec, int64_t V, int nrhs, const Scal* sc, const void* a, const void* b, double* partial,
+             hipStream_t st);
+int blas_copy(int prec, int64_t V, int nrhs, const void* a, void* y, hipStream_t st);
+int blas_to_f32_scaled(int64_t V, int nrhs, const Scal* sc, const void* a64, void* y32, hipStream_t st);
+int blas_to_f64_scaled(int64_t V, int nrhs, const Scal* sc, const void* a32, void* y64, hipStream_t st);
+int blas_finalize(const double* partial, int G, int nrhs, Scal* sc, int kind, hipStream_t st);
+
+// ------------------------------------------------------ domain solves ---
+struct BlockArgs {
+    Geom g;
+    Blocks B;
+    const void* gauge;   // storage precision of the domain solver
+    const void* clover;
+    const void* src;     // projection source
+    size_t src_stride;
+    void* rho;           // workspace float4 [rhs][6][NE]
+    void* q;
+    void* x;
+    size_t ws_stride;    // float4 elements per rhs
+    int NE;              // nblocks * ev
+    int wpb;             // workgroups per domain (split path)
+    void* out;           // K_RAS output (FP32), owned sites
+    size_t out_stride;
+    void* vj;            // optional copy of this sweep's correction (storage precision)
+    size_t vj_stride;
+    int accumulate;      // out += x instead of out = x
+    double kappa, csw;
+    int nrhs;
+    double* partial;     // [rhs][nblocks][wpb][3]
+};
+
+int launch_blk_project(const BlockArgs& a, int src_prec, hipStream_t st);
+int launch_blk_dslash(const BlockArgs& a, int gp, hipStream_t st);
+int launch_blk_update(const BlockArgs& a, int vj_prec, int last, hipStream_t st);
+int launch_blk_unpack(const BlockArgs& a, const float* ws, double* out, hipStream_t st);
+int blas_restart(int prec, int64_t V, int nrhs, const Scal* sc, const void* src, void* r, void* rh, void* p, void* v,
+                 hipStream_t st);

@@ -1,34 +1,700 @@
-// Solvers: RAS preconditioner (Algorithm 1), inner FP32 / outer FP64
-// BiCGStab, plain FP64 BiCGStab.
+// Solvers on the device:
+//   * K_RAS (Algorithm 1 / Eq. (2)): n_ras sweeps of projection, domain
+//     solves, restriction/sum, phi += v and r -= D v (the last residual
+//     update is skipped: it cannot change phi);
+//   * BiCGStab, right-preconditioned (Eq. (3)), batched over right-hand
+//     sides, in FP32 (inner) or FP64 (outer / plain baseline);
+//   * the nested solver of Sec. 3: the FP64 outer BiCGStab's preconditioner
+//     is an FP32 inner BiCGStab preconditioned by K_RAS.  The outer loop
+//     confirms the true residual |eta - D phi| / |eta| in FP64 and restarts
+//     from phi when it is above tolerance.
+// The host only sequences launches and reads the per-rhs scalars once per
+// iteration for the convergence decision.
+#include <cmath>
+#include <functional>
+#include <string>
+#include <vector>
+
 #include "wcl_kernels.h"
 
-struct Workspace {};
+// ----------------------------------------------------------- workspace --
+struct Workspace {
+    wcl_ctx* ctx = nullptr;
+    struct Item {
+        std::string name;
+        void* p;
+        size_t bytes;
+    };
+    std::vector<Item> items;
+    struct Pinned {
+        std::string name;
+        Scal* p;
+        size_t n;
+    };
+    std::vector<Pinned> pinned;   // host mirrors of the scalar arrays, one per solver level
+
+    int get(const std::string& name, size_t bytes, void** out) {
+        for (auto& it : items)
+            if (it.name == name) {
+                if (it.bytes >= bytes) {
+                    *out = it.p;
+                    return WCL_OK;
+                }
+                wcl_dev_free(ctx, it.p, it.bytes);
+                it.p = nullptr;
+                it.bytes = 0;
+                WCL_CHECK(wcl_dev_alloc(ctx, &it.p, bytes));
+                it.bytes = bytes;
+                *out = it.p;
+                return WCL_OK;
+            }
+        Item it{name, nullptr, 0};
+        WCL_CHECK(wcl_dev_alloc(ctx, &it.p, bytes));
+        it.bytes = bytes;
+        items.push_back(it);
+        *out = it.p;
+        return WCL_OK;
+    }
+    int host_scal(const std::string& name, size_t n, Scal** out) {
+        for (auto& pp : pinned)
+            if (pp.name == name) {
+                if (pp.n < n) {
+                    (void)hipHostFree(pp.p);
+                    pp.p = nullptr;
+                    WCL_HIP(hipHostMalloc((void**)&pp.p, n * sizeof(Scal), hipHostMallocDefault));
+                    pp.n = n;
+                }
+                *out = pp.p;
+                return WCL_OK;
+            }
+        Pinned pp{name, nullptr, n};
+        WCL_HIP(hipHostMalloc((void**)&pp.p, n * sizeof(Scal), hipHostMallocDefault));
+        pinned.push_back(pp);
+        *out = pp.p;
+        return WCL_OK;
+    }
+    void release() {
+        for (auto& it : items) wcl_dev_free(ctx, it.p, it.bytes);
+        items.clear();
+        for (auto& pp : pinned) (void)hipHostFree(pp.p);
+        pinned.clear();
+    }
+    ~Workspace() { release(); }
+};
+
+Workspace* wcl_workspace_new(wcl_ctx* ctx) {
+    auto* w = new Workspace;
+    w->ctx = ctx;
+    return w;
+}
+void wcl_workspace_delete(Workspace* w) { delete w; }
 
 void wcl_free_workspace(wcl_lattice* lat) {
     delete lat->ws;
     lat->ws = nullptr;
 }
 
+static Workspace* lattice_ws(wcl_lattice* lat) {
+    if (!lat->ws) lat->ws = wcl_workspace_new(lat->ctx);
+    return lat->ws;
+}
+
+// ---------------------------------------------------------- validation --
+int make_blocks(const wcl_lattice* lat, const wcl_ras_params* p, Blocks* B) {
+    if (!p) {
+        wcl_set_error("RAS parameters missing");
+        return WCL_EINVAL;
+    }
+    if (p->s < 0 || p->n_ras < 1 || p->n_dominv < 1 || (p->storage != WCL_F32 && p->storage != WCL_F16) ||
+        p->kernel < 0 || p->kernel > 2) {
+        wcl_set_error("RAS parameters invalid (s=%d n_ras=%d n_dominv=%d storage=%d kernel=%d)", p->s, p->n_ras,
+                      p->n_dominv, p->storage, p->kernel);
+        return WCL_EINVAL;
+    }
+    B->nblocks = 1;
+    B->ev = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        const int L = lat->g.L[mu], b = p->block[mu];
+        if (b < 1 || L % b != 0) {
+            wcl_set_error("block[%d] = %d does not divide L = %d", mu, b, L);
+            return WCL_EINVAL;
+        }
+        B->b[mu] = b;
+        B->s[mu] = b < L ? p->s : 0;
+        B->e[mu] = b + 2 * B->s[mu];
+        if (B->e[mu] > L) {
+            wcl_set_error("extended block %d + 2*%d exceeds L = %d in direction %d", b, p->s, L, mu);
+            return WCL_EINVAL;
+        }
+        B->nb[mu] = L / b;
+        B->nblocks *= B->nb[mu];
+        B->ev *= B->e[mu];
+    }
+    if ((int64_t)B->nblocks * B->ev * 6 > INT32_MAX) {
+        wcl_set_error("extended domains too large");
+        return WCL_EINVAL;
+    }
+    B->n_ras = p->n_ras;
+    B->n_dominv = p->n_dominv;
+    return WCL_OK;
+}
+
+static int need_fields(const wcl_lattice* lat) {
+    if (!lat->has_clover) {
+        wcl_set_error("gauge and clover fields must be resident");
+        return WCL_ESTATE;
+    }
+    return WCL_OK;
+}
+
+// ------------------------------------------------------------------ RAS --
+static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int storage, double kappa, double csw,
+                     const void* r, void* v, int nrhs, hipStream_t st, wcl_solve_stats* stats) {
+    const int64_t V = lat->V;
+    const size_t s32 = spinor_rhs_bytes(WCL_F32, V), sst = spinor_rhs_bytes(storage, V);
+    const int NE = B.nblocks * B.ev, wpb = (B.ev + 255) / 256;
+    BlockArgs a{};
+    a.g = lat->g;
+    a.B = B;
+    a.gauge = lat->gauge[storage];
+    a.clover = lat->clover[storage];
+    a.NE = NE;
+    a.wpb = wpb;
+    a.ws_stride = (size_t)6 * NE;
+    a.kappa = kappa;
+    a.csw = csw;
+    a.nrhs = nrhs;
+    a.out = v;
+    a.out_stride = s32;
+    const size_t wsb = (size_t)16 * 6 * NE * nrhs;
+    WCL_CHECK(ws->get("ras.rho", wsb, &a.rho));
+    WCL_CHECK(ws->get("ras.q", wsb, &a.q));
+    WCL_CHECK(ws->get("ras.x", wsb, &a.x));
+    WCL_CHECK(ws->get("ras.partial", (size_t)24 * nrhs * B.nblocks * wpb, (void**)&a.partial));
+    void *vj = nullptr, *rbuf[2] = {nullptr, nullptr};
+    if (B.n_ras > 1) {
+        WCL_CHECK(ws->get("ras.vj", sst * nrhs, &vj));
+        WCL_CHECK(ws->get("ras.r0", sst * nrhs, &rbuf[0]));
+        if (B.n_ras > 2) WCL_CHECK(ws->get("ras.r1", sst * nrhs, &rbuf[1]));
+    }
+    for (int j = 0; j < B.n_ras; ++j) {
+        const bool last = j == B.n_ras - 1;
+        const void* src = j == 0 ? r : rbuf[(j - 1) % 2];
+        const int src_prec = j == 0 ? WCL_F32 : storage;
+        a.src = src;
+        a.src_stride = j == 0 ? s32 : sst;
+        a.accumulate = j > 0;
+        a.vj = last ? nullptr : vj;
+        a.vj_stride = sst;
+        // projection r_{Omega'} = P r, then N_dominv MR steps, then R + sum
+        WCL_CHECK(launch_blk_project(a, src_prec, st));
+        for (int k = 0; k < B.n_dominv; ++k) {
+            WCL_CHECK(launch_blk_dslash(a, storage, st));
+            WCL_CHECK(launch_blk_update(a, storage, k == B.n_dominv - 1, st));
+        }
+        if (!last) {
+            // r_{j+1} = r_j - D v_j
+            DslashArgs d{};
+            d.g = lat->g;
+            d.gauge = lat->gauge[storage];
+            d.clover = lat->clover[storage];
+            d.in = vj;
+            d.in_stride = sst;
+            d.y = src;
+            d.y_stride = a.src_stride;
+            d.out = rbuf[j % 2];
+            d.out_stride = sst;
+            d.kappa = kappa;
+            d.csw = csw;
+            d.nrhs = nrhs;
+            WCL_CHECK(launch_dslash(d, storage, storage, storage, DS_AXPY, src_prec, st));
+            if (stats) stats->dslash_full += nrhs;
+        }
+    }
+    if (stats) {
+        stats->ras_sweeps += B.n_ras;
+        stats->dslash_block += (int64_t)B.n_ras * B.n_dominv;
+    }
+    return WCL_OK;
+}
+
+// ------------------------------------------------------------- BiCGStab --
+// Preconditioner: out = K in for the active rhs; sc = the calling engine's
+// device scalars, act = its host-side active flags.
+using Precond = std::function<int(const void* in, void* out, Scal* sc, const std::vector<int>& act)>;
+
+struct EngineResult {
+    int iters = 0;
+    int restarts = 0;
+    bool converged = false;
+    double true_resid = 0.0;   // max over rhs (only with true_check)
+};
+
+struct Engine {
+    wcl_lattice* lat;
+    Workspace* ws;
+    std::string tag;
+    int P;    // vector precision (F64 or F32)
+    int gp;   // link/clover precision of D
+    int nrhs;
+    double kappa, csw;
+    hipStream_t st;
+    wcl_solve_stats* stats;
+    int64_t V;
+    size_t vb;
+    int Gb, Gd;
+    void *r, *rh, *p, *v, *s, *t, *ph, *sh;
+    double* partial;
+    Scal* d;   // device scalars [nrhs]
+    Scal* h;   // pinned host mirror
+
+    int init(const Precond* K) {
+        V = lat->V;
+        vb = spinor_rhs_bytes(P, V) * nrhs;
+        Gb = blas_partials(P, V);
+        Gd = dslash_partials_per_rhs((int)V);
+        auto name = [&](const char* n) { return tag + "." + n; };
+        WCL_CHECK(ws->get(name("r"), vb, &r));
+        WCL_CHECK(ws->get(name("rh"), vb, &rh));
+        WCL_CHECK(ws->get(name("p"), vb, &p));
+        WCL_CHECK(ws->get(name("v"), vb, &v));
+        WCL_CHECK(ws->get(name("s"), vb, &s));
+        WCL_CHECK(ws->get(name("t"), vb, &t));
+        if (K) {
+            WCL_CHECK(ws->get(name("ph"), vb, &ph));
+            WCL_CHECK(ws->get(name("sh"), vb, &sh));
+        } else {
+            ph = p;
+            sh = s;
+        }
+        WCL_CHECK(ws->get(name("partial"), (size_t)24 * nrhs * std::max(Gb, Gd), (void**)&partial));
+        WCL_CHECK(ws->get(name("scal"), sizeof(Scal) * nrhs, (void**)&d));
+        return WCL_OK;
+    }
+    int apply_dot(const void* in, void* out, const void* a) {
+        DslashArgs x{};
+        x.g = lat->g;
+        x.gauge = lat->gauge[gp];
+        x.clover = lat->clover[gp];
+        x.in = in;
+        x.out = out;
+        x.a = a;
+        x.in_stride = x.out_stride = x.a_stride = spinor_rhs_bytes(P, V);
+        x.kappa = kappa;
+        x.csw = csw;
+        x.nrhs = nrhs;
+        x.partial = partial;
+        if (stats) stats->dslash_full += nrhs;
+        return launch_dslash(x, gp, P, P, DS_DOT, P, st);
+    }
+    // out = b - D x (FP64 true residual)
+    int residual(const void* b, const void* x, void* out) {
+        DslashArgs a{};
+        a.g = lat->g;
+        a.gauge = lat->gauge[gp];
+        a.clover = lat->clover[gp];
+        a.in = x;
+        a.y = b;
+        a.out = out;
+        a.in_stride = a.out_stride = a.y_stride = spinor_rhs_bytes(P, V);
+        a.kappa = kappa;
+        a.csw = csw;
+        a.nrhs = nrhs;
+        if (stats) stats->dslash_full += nrhs;
+        return launch_dslash(a, gp, P, P, DS_AXPY, P, st);
+    }
+    int pull() {
+        WCL_HIP(hipMemcpyAsync(h, d, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st));
+        WCL_HIP(hipStreamSynchronize(st));
+        return WCL_OK;
+    }
+    int push() {
+        WCL_HIP(hipMemcpyAsync(d, h, sizeof(Scal) * nrhs, hipMemcpyHostToDevice, st));
+        WCL_HIP(hipStreamSynchronize(st));
+        return WCL_OK;
+    }
+
+    // Solves A x = b (A = D at precision gp) for the rhs with act[i] = 1.
+    // On return act[i] = 1 marks the rhs that converged.
+    int run(const void* b, void* x, double tol, int max_iter, const Precond* K, std::vector<int>& act, bool true_check,
+            int max_restarts, EngineResult* res) {
+        WCL_CHECK(init(K));
+        WCL_CHECK(ws->host_scal(tag, nrhs, &h));
+        WCL_CHECK(blas_copy(P, V, nrhs, nullptr, x, st));
+        WCL_CHECK(blas_copy(P, V, nrhs, b, r, st));
+        WCL_CHECK(blas_copy(P, V, nrhs, b, rh, st));
+        WCL_CHECK(blas_copy(P, V, nrhs, nullptr, p, st));
+        WCL_CHECK(blas_copy(P, V, nrhs, nullptr, v, st));
+        for (int i = 0; i < nrhs; ++i) {
+            Scal z{};
+            z.rho[0] = z.rho_old[0] = z.alpha[0] = z.omega[0] = 1.0;
+            z.active = act[i];
+            h[i] = z;
+        }
+        WCL_CHECK(push());
+        WCL_CHECK(blas_dot(P, V, nrhs, d, rh, r, partial, st));
+        WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RHO, st));
+        WCL_CHECK(pull());
+        std::vector<double> bnorm(nrhs, 0.0), rh2(nrhs, 0.0);
+        std::vector<int> conv(nrhs, 0), restarts(nrhs, 0);
+        for (int i = 0; i < nrhs; ++i) {
+            if (!act[i]) continue;
+            if (!std::isfinite(h[i].rr)) {
+                wcl_set_error("right-hand side %d is not finite", i);
+                return WCL_EINVAL;
+            }
+            bnorm[i] = std::sqrt(h[i].rr);
+            rh2[i] = h[i].rr;
+            h[i].rho_old[0] = 1.0;
+            h[i].rho_old[1] = 0.0;
+            if (bnorm[i] == 0.0) {  // b = 0: x = 0 is exact
+                h[i].active = 0;
+                conv[i] = 1;
+            }
+        }
+        WCL_CHECK(push());
+        int it = 0, total_restarts = 0;
+        auto any_active = [&]() {
+            for (int i = 0; i < nrhs; ++i)
+                if (h[i].active) return true;
+            return false;
+        };
+        while (any_active() && it < max_iter) {
+            ++it;
+            WCL_CHECK(blas_p_update(P, V, nrhs, d, r, p, v, partial, st));
+            std::vector<int> a_now(nrhs);
+            for (int i = 0; i < nrhs; ++i) a_now[i] = h[i].active;
+            if (K) WCL_CHECK((*K)(p, ph, d, a_now));
+            WCL_CHECK(apply_dot(ph, v, rh));
+            WCL_CHECK(blas_finalize(partial, Gd, nrhs, d, FIN_ALPHA, st));
+            WCL_CHECK(blas_s_update(P, V, nrhs, d, r, v, s, st));
+            if (K) WCL_CHECK((*K)(s, sh, d, a_now));
+            WCL_CHECK(apply_dot(sh, t, s));
+            WCL_CHECK(blas_finalize(partial, Gd, nrhs, d, FIN_OMEGA, st));
+            WCL_CHECK(blas_xr_update(P, V, nrhs, d, x, ph, sh, s, t, r, rh, partial, st));
+            WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RHO, st));
+            WCL_CHECK(pull());
+            bool changed = false, want_true = false;
+            std::vector<int> restart(nrhs, 0);
+            for (int i = 0; i < nrhs; ++i) {
+                if (!h[i].active) continue;
+                const double rr = h[i].rr;
+                if (!std::isfinite(rr)) {
+                    h[i].active = 0;
+                    changed = true;
+                    continue;
+                }
+                const double rel = std::sqrt(rr) / bnorm[i];
+                if (rel <= tol) {
+                    if (true_check) {
+                        want_true = true;
+                        restart[i] = 3;   // candidate
+                    } else {
+                        h[i].active = 0;
+                        conv[i] = 1;
+                        changed = true;
+                    }
+                } else {
+                    const double arho = std::hypot(h[i].rho[0], h[i].rho[1]);
+                    const bool bd = h[i].breakdown || arho < 1e-30 * std::sqrt(rh2[i] * rr) ||
+                                    (h[i].omega[0] == 0.0 && h[i].omega[1] == 0.0);
+                    if (bd) restart[i] = 1;
+                }
+            }
+            const void* restart_src = nullptr;
+            if (want_true) {
+                // true residual in the engine's precision: t = b - D x
+                WCL_CHECK(residual(b, x, t));
+                WCL_CHECK(blas_dot(P, V, nrhs, d, t, t, partial, st));
+                WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RR, st));
+                WCL_CHECK(pull());
+                for (int i = 0; i < nrhs; ++i) {
+                    if (restart[i] != 3) continue;
+                    const double trel = std::sqrt(h[i].rr) / bnorm[i];
+                    if (trel <= tol) {
+                        h[i].active = 0;
+                        conv[i] = 1;
+                        restart[i] = 0;
+                        changed = true;
+                    } else if (restarts[i] < max_restarts) {
+                        restart[i] = 2;   // defect correction from the true residual
+                        restart_src = t;
+                    } else {
+                        h[i].active = 0;
+                        restart[i] = 0;
+                        changed = true;
+                    }
+                }
+            }
+            bool any_restart = false;
+            for (int i = 0; i < nrhs; ++i)
+                if (restart[i] == 1 || restart[i] == 2) {
+                    if (restart[i] == 1 && restarts[i] >= max_restarts + 50) {
+                        h[i].active = 0;   // persistent breakdown
+                        changed = true;
+                        continue;
+                    }
+                    any_restart = true;
+                    ++restarts[i];
+                    ++total_restarts;
+                }
+            if (any_restart) {
+                // rhs restarting from the recursive residual keep r; those
+                // restarting from the true residual take r = t.  Two passes
+                // when both kinds occur.
+                for (int pass = 0; pass < 2; ++pass) {
+                    const int kind = pass == 0 ? 1 : 2;
+                    bool any = false;
+                    for (int i = 0; i < nrhs; ++i) {
+                        h[i].breakdown = (restart[i] == kind && h[i].active) ? 2 : 0;
+                        any = any || h[i].breakdown == 2;
+                    }
+                    if (!any) continue;
+                    WCL_CHECK(push());
+                    WCL_CHECK(blas_restart(P, V, nrhs, d, kind == 2 ? restart_src : nullptr, r, rh, p, v, st));
+                }
+                for (int i = 0; i < nrhs; ++i) h[i].breakdown = 0;
+                WCL_CHECK(push());
+                WCL_CHECK(blas_dot(P, V, nrhs, d, rh, r, partial, st));
+                WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RHO, st));
+                WCL_CHECK(pull());
+                for (int i = 0; i < nrhs; ++i) {
+                    if (restart[i] != 1 && restart[i] != 2) continue;
+                    h[i].rho_old[0] = h[i].alpha[0] = h[i].omega[0] = 1.0;
+                    h[i].rho_old[1] = h[i].alpha[1] = h[i].omega[1] = 0.0;
+                    rh2[i] = h[i].rr;
+                }
+                changed = true;
+            }
+            if (changed) WCL_CHECK(push());
+        }
+        res->iters = it;
+        res->restarts = total_restarts;
+        res->converged = true;
+        for (int i = 0; i < nrhs; ++i) {
+            if (act[i] && !conv[i]) res->converged = false;
+            act[i] = conv[i];
+        }
+        if (true_check) {
+            // report |b - D x| / |b| for every rhs
+            for (int i = 0; i < nrhs; ++i) h[i].active = bnorm[i] > 0 ? 1 : 0;
+            WCL_CHECK(push());
+            WCL_CHECK(residual(b, x, t));
+            WCL_CHECK(blas_dot(P, V, nrhs, d, t, t, partial, st));
+            WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RR, st));
+            WCL_CHECK(pull());
+            res->true_resid = 0.0;
+            for (int i = 0; i < nrhs; ++i)
+                if (bnorm[i] > 0) res->true_resid = std::max(res->true_resid, std::sqrt(h[i].rr) / bnorm[i]);
+        }
+        return WCL_OK;
+    }
+};
+
+static int check_solver_params(const wcl_solver_params* p) {
+    if (!p || !(p->tol_outer > 0) || !(p->tol_inner > 0) || p->max_outer < 1 || p->max_inner < 1 ||
+        p->max_restarts < 0 || (p->precond != WCL_PRECOND_NONE && p->precond != WCL_PRECOND_RAS)) {
+        wcl_set_error("invalid solver parameters");
+        return WCL_EINVAL;
+    }
+    return WCL_OK;
+}
+
+// The nested solve on an explicit workspace (used by the C ABI with the
+// lattice's own workspace and by the serving loop with per-slot ones).
+int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, double kappa, double csw,
+                 const void* eta, void* phi, int nrhs, wcl_solve_stats* stats, hipStream_t st) {
+    WCL_CHECK(check_solver_params(prm));
+    WCL_CHECK(need_fields(lat));
+    if (!eta || !phi || nrhs < 1 || !std::isfinite(kappa) || !std::isfinite(csw)) {
+        wcl_set_error("wcl_solve_nested_bicgstab: bad argument");
+        return WCL_EINVAL;
+    }
+    Blocks B{};
+    const bool use_ras = prm->precond == WCL_PRECOND_RAS;
+    if (use_ras) WCL_CHECK(make_blocks(lat, &prm->ras, &B));
+    const int storage = prm->ras.storage;
+    wcl_solve_stats local{};
+    wcl_solve_stats* S = stats ? stats : &local;
+    *S = wcl_solve_stats{};
+    hipEvent_t e0, e1;
+    WCL_HIP(hipEventCreate(&e0));
+    WCL_HIP(hipEventCreate(&e1));
+    WCL_HIP(hipEventRecord(e0, st));
+
+    Engine inner{lat, ws, "in", WCL_F32, WCL_F32, nrhs, kappa, csw, st, S};
+    void *b32 = nullptr, *y32 = nullptr;
+    const size_t v32 = spinor_rhs_bytes(WCL_F32, lat->V) * nrhs;
+    WCL_CHECK(ws->get("nest.b32", v32, &b32));
+    WCL_CHECK(ws->get("nest.y32", v32, &y32));
+    Precond Kras = [&](const void* in, void* out, Scal*, const std::vector<int>&) -> int {
+        return ras_apply(lat, ws, B, storage, kappa, csw, in, out, nrhs, st, S);
+    };
+    Engine outer{lat, ws, "out", WCL_F64, WCL_F64, nrhs, kappa, csw, st, S};
+    int outer_partials_G = blas_partials(WCL_F64, lat->V);
+    Precond Kinner = [&](const void* in, void* out, Scal* sc, const std::vector<int>& act) -> int {
+        // b = in/|in| in FP32, inner solve, out = |in| y in FP64
+        WCL_CHECK(blas_dot(WCL_F64, lat->V, nrhs, sc, in, in, outer.partial, st));
+        WCL_CHECK(blas_finalize(outer.partial, outer_partials_G, nrhs, sc, FIN_PP, st));
+        WCL_CHECK(blas_to_f32_scaled(lat->V, nrhs, sc, in, b32, st));
+        std::vector<int> a = act;
+        EngineResult r;
+        WCL_CHECK(inner.run(b32, y32, prm->tol_inner, prm->max_inner, use_ras ? &Kras : nullptr, a, false, 0, &r));
+        S->inner_iters += r.iters;
+        WCL_CHECK(blas_to_f64_scaled(lat->V, nrhs, sc, y32, out, st));
+        return WCL_OK;
+    };
+    std::vector<int> act(nrhs, 1);
+    EngineResult res;
+    int rc = outer.run(eta, phi, prm->tol_outer, prm->max_outer, &Kinner, act, true, prm->max_restarts, &res);
+    WCL_HIP(hipEventRecord(e1, st));
+    WCL_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    WCL_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != WCL_OK) return rc;
+    S->outer_iters = res.iters;
+    S->restarts += res.restarts;
+    S->converged = res.converged;
+    S->true_resid = res.true_resid;
+    S->ms_total = ms;
+    if (!res.converged || !(res.true_resid <= prm->tol_outer)) {
+        S->converged = 0;
+        wcl_set_error("nested BiCGStab: true residual %.3e above tolerance %.3e after %d outer iterations",
+                      res.true_resid, prm->tol_outer, res.iters);
+        return WCL_ENOTCONV;
+    }
+    return WCL_OK;
+}
+
 extern "C" {
-int wcl_block_info(const wcl_lattice*, const wcl_ras_params*, int64_t*, int64_t*) {
-    wcl_set_error("not implemented");
-    return WCL_ESTATE;
+
+int wcl_block_info(const wcl_lattice* lat, const wcl_ras_params* ras, int64_t* nblocks, int64_t* ext_volume) {
+    if (!lat || !nblocks || !ext_volume) return WCL_EINVAL;
+    Blocks B;
+    WCL_CHECK(make_blocks(lat, ras, &B));
+    *nblocks = B.nblocks;
+    *ext_volume = B.ev;
+    return WCL_OK;
 }
-int wcl_apply_D_blocks(wcl_lattice*, const wcl_ras_params*, double, double, const void*, double*, void*) {
-    wcl_set_error("not implemented");
-    return WCL_ESTATE;
+
+int wcl_apply_D_blocks(wcl_lattice* lat, const wcl_ras_params* ras, double kappa, double csw, const void* in_dev,
+                       double* out_host, void* stream) {
+    if (!lat || !in_dev || !out_host) {
+        wcl_set_error("wcl_apply_D_blocks: null argument");
+        return WCL_EINVAL;
+    }
+    WCL_CHECK(need_fields(lat));
+    Blocks B;
+    WCL_CHECK(make_blocks(lat, ras, &B));
+    WCL_HIP(hipSetDevice(lat->ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    Workspace* ws = lattice_ws(lat);
+    BlockArgs a{};
+    a.g = lat->g;
+    a.B = B;
+    a.gauge = lat->gauge[ras->storage];
+    a.clover = lat->clover[ras->storage];
+    a.NE = B.nblocks * B.ev;
+    a.wpb = (B.ev + 255) / 256;
+    a.ws_stride = (size_t)6 * a.NE;
+    a.kappa = kappa;
+    a.csw = csw;
+    a.nrhs = 1;
+    a.src = in_dev;
+    a.src_stride = spinor_rhs_bytes(WCL_F32, lat->V);
+    const size_t wsb = (size_t)16 * 6 * a.NE;
+    WCL_CHECK(ws->get("ras.rho", wsb, &a.rho));
+    WCL_CHECK(ws->get("ras.q", wsb, &a.q));
+    WCL_CHECK(ws->get("ras.x", wsb, &a.x));
+    WCL_CHECK(ws->get("ras.partial", (size_t)24 * B.nblocks * a.wpb, (void**)&a.partial));
+    void* stage = nullptr;
+    const size_t ob = (size_t)a.NE * 24 * sizeof(double);
+    WCL_CHECK(ws->get("blocks.out", ob, &stage));
+    WCL_CHECK(launch_blk_project(a, WCL_F32, st));
+    WCL_CHECK(launch_blk_dslash(a, ras->storage, st));
+    WCL_CHECK(launch_blk_unpack(a, (const float*)a.q, (double*)stage, st));
+    WCL_HIP(hipMemcpyAsync(out_host, stage, ob, hipMemcpyDeviceToHost, st));
+    WCL_HIP(hipStreamSynchronize(st));
+    return WCL_OK;
 }
-int wcl_ras_precondition(wcl_lattice*, const wcl_ras_params*, double, double, const void*, void*, int, void*) {
-    wcl_set_error("not implemented");
-    return WCL_ESTATE;
+
+int wcl_ras_precondition(wcl_lattice* lat, const wcl_ras_params* ras, double kappa, double csw, const void* r_dev,
+                         void* v_dev, int nrhs, void* stream) {
+    if (!lat || !r_dev || !v_dev || r_dev == v_dev || nrhs < 1) {
+        wcl_set_error("wcl_ras_precondition: bad argument");
+        return WCL_EINVAL;
+    }
+    WCL_CHECK(need_fields(lat));
+    Blocks B;
+    WCL_CHECK(make_blocks(lat, ras, &B));
+    WCL_HIP(hipSetDevice(lat->ctx->device));
+    return ras_apply(lat, lattice_ws(lat), B, ras->storage, kappa, csw, r_dev, v_dev, nrhs, (hipStream_t)stream,
+                     nullptr);
 }
-int wcl_solve_nested_bicgstab(wcl_lattice*, const wcl_solver_params*, double, double, const void*, void*, int,
-                              wcl_solve_stats*, void*) {
-    wcl_set_error("not implemented");
-    return WCL_ESTATE;
+
+int wcl_solve_nested_bicgstab(wcl_lattice* lat, const wcl_solver_params* p, double kappa, double csw,
+                              const void* eta_dev, void* phi_dev, int nrhs, wcl_solve_stats* stats, void* stream) {
+    if (!lat) return WCL_EINVAL;
+    WCL_HIP(hipSetDevice(lat->ctx->device));
+    return nested_solve(lat, lattice_ws(lat), p, kappa, csw, eta_dev, phi_dev, nrhs, stats, (hipStream_t)stream);
 }
-int wcl_solve_bicgstab_f64(wcl_lattice*, double, int, double, double, const void*, void*, wcl_solve_stats*, void*) {
-    wcl_set_error("not implemented");
-    return WCL_ESTATE;
+
+int wcl_solve_bicgstab_f64(wcl_lattice* lat, double tol, int max_iter, double kappa, double csw, const void* eta_dev,
+                           void* phi_dev, wcl_solve_stats* stats, void* stream) {
+    if (!lat || !eta_dev || !phi_dev || !(tol > 0) || max_iter < 1) {
+        wcl_set_error("wcl_solve_bicgstab_f64: bad argument");
+        return WCL_EINVAL;
+    }
+    WCL_CHECK(need_fields(lat));
+    WCL_HIP(hipSetDevice(lat->ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    wcl_solve_stats local{};
+    wcl_solve_stats* S = stats ? stats : &local;
+    *S = wcl_solve_stats{};
+    hipEvent_t e0, e1;
+    WCL_HIP(hipEventCreate(&e0));
+    WCL_HIP(hipEventCreate(&e1));
+    WCL_HIP(hipEventRecord(e0, st));
+    Engine eng{lat, lattice_ws(lat), "plain", WCL_F64, WCL_F64, 1, kappa, csw, st, S};
+    std::vector<int> act(1, 1);
+    EngineResult res;
+    // plain solver: stop on the recursive residual, no restart; report the true residual
+    int rc = eng.run(eta_dev, phi_dev, tol, max_iter, nullptr, act, false, 0, &res);
+    if (rc == WCL_OK) {
+        // true residual for the report
+        eng.h[0].active = 1;
+        rc = eng.push();
+        if (rc == WCL_OK) rc = eng.residual(eta_dev, phi_dev, eng.t);
+        if (rc == WCL_OK) rc = blas_dot(WCL_F64, lat->V, 1, eng.d, eng.t, eng.t, eng.partial, st);
+        if (rc == WCL_OK) rc = blas_finalize(eng.partial, eng.Gb, 1, eng.d, FIN_RR, st);
+        if (rc == WCL_OK) rc = eng.pull();
+        if (rc == WCL_OK) {
+            // |eta|: reuse the dot on the right-hand side
+            double rr = eng.h[0].rr;
+            rc = blas_dot(WCL_F64, lat->V, 1, eng.d, eta_dev, eta_dev, eng.partial, st);
+            if (rc == WCL_OK) rc = blas_finalize(eng.partial, eng.Gb, 1, eng.d, FIN_RR, st);
+            if (rc == WCL_OK) rc = eng.pull();
+            if (rc == WCL_OK) S->true_resid = eng.h[0].rr > 0 ? std::sqrt(rr / eng.h[0].rr) : 0.0;
+        }
+    }
+    WCL_HIP(hipEventRecord(e1, st));
+    WCL_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    WCL_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != WCL_OK) return rc;
+    S->outer_iters = res.iters;
+    S->restarts = res.restarts;
+    S->converged = res.converged;
+    S->ms_total = ms;
+    if (!res.converged) {
+        wcl_set_error("BiCGStab FP64: not converged after %d iterations", res.iters);
+        return WCL_ENOTCONV;
+    }
+    return WCL_OK;
 }
-}
+
+}  // extern "C"
