@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--overlap", type=int, default=0, help="RAS overlap s (depth d = 2s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dapply", action="store_true")
+    ap.add_argument("--mode", default="full", choices=["full", "dapply", "copyref"],
+                    help="dapply: only the 32^4 FP32 D-apply loop; copyref: a 1 GiB device copy "
+                         "(the reference kernel for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     return ap.parse_args()
 
 
@@ -100,6 +103,32 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "copyref":
+        n = 1 << 30
+        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(5):
+            b.copy_(a)
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / 5
+        print(json.dumps({"mode": "copyref", "bytes_read_per_copy": n, "bytes_written_per_copy": n, "copies": 6,
+                          "ms_per_copy": ms, "GBps_read_plus_write": 2 * n / ms / 1e6}))
+        return
+    if args.mode == "dapply":
+        ctx = W.Context(0)
+        big = (32, 32, 32, 32)
+        lb = W.Lattice(ctx, big)
+        lb.upload_gauge(I.random_gauge(big, 1.0, 1))
+        us = time_dapply(W, torch, lb, 1, n_warm=3, n_timed=10)
+        print(json.dumps({"mode": "dapply", "V": lb.V, "us": us, "launches": 13}))
+        lb.close()
+        ctx.close()
+        return
     dims = (16, 16, 16, 32)
     kappa, csw, tol = 0.125, 1.0, 1e-10
     block, s, nd, nras = (8, 8, 8, 8), args.overlap, 4, 3

@@ -144,6 +144,13 @@ int wcl_create_lattice(wcl_ctx* ctx, const int dims[4], const int bc[4], wcl_lat
     }
     g.Vc = g.S * dims[3];
     g.V = (int)V;
+    // lanes per site of the D-apply (1, 2 or 4); one lane per site measured
+    // fastest on 16^3x32 and 32^4; WCL_DSLASH_LPS overrides it
+    lat->lps = 1;
+    if (const char* e = getenv("WCL_DSLASH_LPS")) {
+        int v = atoi(e);
+        if (v == 1 || v == 2 || v == 4) lat->lps = v;
+    }
     *out = lat;
     return WCL_OK;
 }
@@ -376,6 +383,7 @@ int wcl_apply_D(wcl_lattice* lat, int prec, double kappa, double csw, const void
     a.kappa = kappa;
     a.csw = csw;
     a.nrhs = nrhs;
+    a.lps = lat->lps;
     return launch_dslash(a, prec, prec, prec, DS_PLAIN, prec, (hipStream_t)stream);
 }
 

@@ -264,3 +264,205 @@ int launch_blk_unpack(const BlockArgs& a, const float* ws, double* out, hipStrea
     WCL_HIP(hipGetLastError());
     return WCL_OK;
 }
+
+// ----------------------------------------------------------- fused path --
+// One workgroup per (domain, rhs) holds the whole extended domain on chip:
+// extended site l is thread l; its two-row links U_mu(x) and its clover
+// block pair stay in registers for all N_dominv MR steps, and each step
+// publishes rho(x) and the backward-hop half-spinors U_mu(x)^dag P+ rho(x)
+// in LDS for the neighbours.  Two barriers per step; alpha comes from a
+// fixed-order workgroup all-reduce, so every thread holds the same value.
+template <int NW>
+WCL_DEV void wg_allreduce3(double d[3], double* sh) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d[k] = wave_sum(d[k]);
+    if (l == 0)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sh[3 * w + k] = d[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) s += sh[3 * q + k];
+        d[k] = s;
+    }
+}
+
+template <int MU>
+WCL_DEV void rebuild_link(const float u12[12], float u[18]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) u[k] = u12[k];
+    reconstruct_row2(u);
+}
+
+template <int GP, int SRC, int VP, int NT>
+__global__ __launch_bounds__(NT) void k_blk_fused(BlockArgs a, int write_vj) {
+    extern __shared__ float lds[];
+    float* s_rho = lds;                 // [24][NT]
+    float* s_bwd = lds + 24 * NT;       // [4][12][NT]
+    __shared__ double s_red[3 * (NT / 64)];
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int rhs = lb % a.nrhs, blk = lb / a.nrhs;
+    const int l = threadIdx.x;
+    const bool active = l < a.B.ev;
+    int lc[4] = {0, 0, 0, 0}, x[4] = {0, 0, 0, 0}, gi = 0;
+    int nf[4], nb[4];
+    float phf[4], phb[4];
+    float rho[24], xs[24], u12[4][12] = {}, c[72] = {};
+#pragma unroll
+    for (int k = 0; k < 24; ++k) {
+        rho[k] = 0.f;
+        xs[k] = 0.f;
+    }
+    if (active) {
+        block_site(a.g, a.B, blk, l, lc, x);
+        gi = geom_index(a.g, x);
+        SpinorIO<SRC>::load((const char*)a.src + rhs * a.src_stride, a.g.V, gi, rho);   // projection P r
+        float u[18];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            GaugeIO<GP>::load(a.gauge, a.g.V, mu, gi, u);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) u12[mu][k] = u[k];
+        }
+        CloverIO<GP>::load(a.clover, a.g.V, gi, c);
+    }
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        int ln[4] = {lc[0], lc[1], lc[2], lc[3]};
+        const int e = a.B.e[mu], L = a.g.L[mu];
+        // forward neighbour inside Omega'?
+        ln[mu] = lc[mu] + 1;
+        bool in = true;
+        if (ln[mu] == e) {
+            if (e == L) ln[mu] = 0;
+            else in = false;
+        }
+        nf[mu] = (active && in) ? local_index(a.B, ln) : -1;
+        phf[mu] = (x[mu] == L - 1) ? (float)a.g.bc[mu] : 1.f;
+        ln[mu] = lc[mu] - 1;
+        in = true;
+        if (ln[mu] < 0) {
+            if (e == L) ln[mu] = e - 1;
+            else in = false;
+        }
+        nb[mu] = (active && in) ? local_index(a.B, ln) : -1;
+        phb[mu] = (x[mu] == 0) ? (float)a.g.bc[mu] : 1.f;
+    }
+    const float ck = (float)(a.csw * a.kappa), mk = (float)(-a.kappa);
+    // rho lives in LDS between steps: only its owner thread writes it
+#pragma unroll
+    for (int k = 0; k < 24; ++k) s_rho[k * NT + l] = rho[k];
+    for (int step = 0; step < a.B.n_dominv; ++step) {
+        // publish the backward-hop contributions U_mu(x)^dag P+ rho(x)
+        {
+            float r[24], h[12], w[12], u[18];
+#pragma unroll
+            for (int k = 0; k < 24; ++k) r[k] = s_rho[k * NT + l];
+#define WCL_BWD(MU)                                                         \
+    spin_project<MU, false>(r, h);                                          \
+    rebuild_link<MU>(u12[MU], u);                                           \
+    su3_apply2<true>(u, h, w);                                              \
+    _Pragma("unroll") for (int k = 0; k < 12; ++k) s_bwd[(MU * 12 + k) * NT + l] = w[k];
+            WCL_BWD(0) WCL_BWD(1) WCL_BWD(2) WCL_BWD(3)
+#undef WCL_BWD
+        }
+        __syncthreads();
+        // q = D_{Omega'} rho
+        float q[24];
+        {
+            float r[24];
+#pragma unroll
+            for (int k = 0; k < 24; ++k) r[k] = s_rho[k * NT + l];
+            clover_term(c, r, ck, q);
+        }
+        {
+            float s[24], h[12], w[12], u[18];
+#define WCL_HOPS(MU)                                                                            \
+    if (nf[MU] >= 0) {                                                                          \
+        _Pragma("unroll") for (int k = 0; k < 24; ++k) s[k] = s_rho[k * NT + nf[MU]];         \
+        spin_project<MU, true>(s, h);                                                           \
+        rebuild_link<MU>(u12[MU], u);                                                           \
+        su3_apply2<false>(u, h, w);                                                             \
+        spin_accumulate<MU, true>(w, mk * phf[MU], q);                                          \
+    }                                                                                           \
+    if (nb[MU] >= 0) {                                                                          \
+        _Pragma("unroll") for (int k = 0; k < 12; ++k) w[k] = s_bwd[(MU * 12 + k) * NT + nb[MU]]; \
+        spin_accumulate<MU, false>(w, mk * phb[MU], q);                                         \
+    }
+            WCL_HOPS(0) WCL_HOPS(1) WCL_HOPS(2) WCL_HOPS(3)
+#undef WCL_HOPS
+        }
+        double d[3] = {0.0, 0.0, 0.0};
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const float qr = q[2 * k], qi = q[2 * k + 1];
+                const float rr = s_rho[(2 * k) * NT + l], ri = s_rho[(2 * k + 1) * NT + l];
+                d[0] += (double)(qr * rr + qi * ri);
+                d[1] += (double)(qr * ri - qi * rr);
+                d[2] += (double)(qr * qr + qi * qi);
+            }
+        }
+        // every thread has finished reading rho and the backward terms after this barrier
+        wg_allreduce3<NT / 64>(d, s_red);
+        const float ar = d[2] > 0 ? (float)(d[0] / d[2]) : 0.f;
+        const float ai = d[2] > 0 ? (float)(d[1] / d[2]) : 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const float pr = s_rho[(2 * k) * NT + l], pi = s_rho[(2 * k + 1) * NT + l];
+            xs[2 * k] += ar * pr - ai * pi;
+            xs[2 * k + 1] += ar * pi + ai * pr;
+            s_rho[(2 * k) * NT + l] = pr - (ar * q[2 * k] - ai * q[2 * k + 1]);
+            s_rho[(2 * k + 1) * NT + l] = pi - (ar * q[2 * k + 1] + ai * q[2 * k]);
+        }
+        __syncthreads();
+    }
+    // restriction to the owned sites and sum into the output
+    if (!active || !block_owned(a.B, lc)) return;
+    char* out = (char*)a.out + rhs * a.out_stride;
+    if (a.accumulate) {
+        float o[24];
+        SpinorIO<WCL_F32>::load(out, a.g.V, gi, o);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) o[k] += xs[k];
+        SpinorIO<WCL_F32>::store(out, a.g.V, gi, o);
+    } else {
+        SpinorIO<WCL_F32>::store(out, a.g.V, gi, xs);
+    }
+    if (write_vj) SpinorIO<VP>::store((char*)a.vj + rhs * a.vj_stride, a.g.V, gi, xs);
+}
+
+int fused_threads(int ev) { return ev <= 256 ? 256 : (ev <= 512 ? 512 : 0); }
+
+template <int GP, int SRC, int VP, int NT>
+static int launch_fused_t(const BlockArgs& a, hipStream_t st) {
+    const size_t lds = (size_t)72 * NT * sizeof(float);
+    static bool attr = false;   // dynamic LDS above the 64 KB default
+    if (!attr) {
+        WCL_HIP(hipFuncSetAttribute((const void*)k_blk_fused<GP, SRC, VP, NT>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr = true;
+    }
+    k_blk_fused<GP, SRC, VP, NT><<<a.B.nblocks * a.nrhs, NT, lds, st>>>(a, a.vj != nullptr);
+    WCL_HIP(hipGetLastError());
+    return WCL_OK;
+}
+
+int launch_blk_fused(const BlockArgs& a, int gp, int src_prec, hipStream_t st) {
+    const int nt = fused_threads(a.B.ev);
+#define WCL_F(G, S, NT) \
+    if (gp == G && src_prec == S && nt == NT) return launch_fused_t<G, S, G, NT>(a, st)
+    WCL_F(WCL_F32, WCL_F32, 256);
+    WCL_F(WCL_F32, WCL_F32, 512);
+    WCL_F(WCL_F16, WCL_F32, 256);
+    WCL_F(WCL_F16, WCL_F32, 512);
+    WCL_F(WCL_F16, WCL_F16, 256);
+    WCL_F(WCL_F16, WCL_F16, 512);
+#undef WCL_F
+    wcl_set_error("fused domain solver: unsupported case (storage %d, source %d, extended volume %d)", gp, src_prec,
+                  a.B.ev);
+    return WCL_EINVAL;
+}

@@ -413,3 +413,79 @@ WCL_DEV void block_reduce3(double d[3], double* out) {
         }
     }
 }
+
+// ------------------------------------------- direction-generic stencil --
+// Same projections as spin_project / spin_accumulate, but with mu chosen at
+// run time, so that the lanes of one wavefront can take different
+// directions without diverging.  In the chiral basis
+//   (1 -+ gamma_mu) psi:  h0 = u0 + c0 l_p0,  h1 = u1 + c1 l_p1,
+//   lower spins       :  (d0 w_q0, d1 w_q1),  q = p,
+// with, for the forward hop (1 - gamma_mu) (backward: c, d negated),
+//   mu :  c0   c1   p0  d0   d1
+//   x  :  i    i    1   -i   -i
+//   y  :  1    -1   1   -1   1
+//   z  :  i    -i   0   -i   i
+//   t  :  1    1    0   1    1
+struct RtCoef {
+    float c0r, c0i, c1r, c1i, d0r, d0i, d1r, d1i;
+    int p0;
+};
+
+WCL_DEV RtCoef rt_coef(int mu, bool fwd) {
+    RtCoef k;
+    const float s = fwd ? 1.f : -1.f;
+    const bool ev = (mu & 1) == 0;
+    k.c0r = ev ? 0.f : s;
+    k.c0i = ev ? s : 0.f;
+    k.c1r = mu == 0 ? 0.f : (mu == 1 ? -s : (mu == 2 ? 0.f : s));
+    k.c1i = mu == 0 ? s : (mu == 2 ? -s : 0.f);
+    k.d0r = mu == 1 ? -s : (mu == 3 ? s : 0.f);
+    k.d0i = (mu == 0 || mu == 2) ? -s : 0.f;
+    k.d1r = (mu == 1 || mu == 3) ? s : 0.f;
+    k.d1i = mu == 0 ? -s : (mu == 2 ? s : 0.f);
+    k.p0 = mu < 2 ? 1 : 0;
+    return k;
+}
+
+template <typename T>
+WCL_DEV void spin_project_rt(const RtCoef& k, const T s[24], T h[12]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int r = 2 * c, i = 2 * c + 1;
+        const T l0r = s[12 + r], l0i = s[12 + i], l1r = s[18 + r], l1i = s[18 + i];
+        const T ar = k.p0 ? l1r : l0r, ai = k.p0 ? l1i : l0i;   // l_p0
+        const T br = k.p0 ? l0r : l1r, bi = k.p0 ? l0i : l1i;   // l_p1
+        h[r] = s[r] + (T)k.c0r * ar - (T)k.c0i * ai;
+        h[i] = s[i] + (T)k.c0r * ai + (T)k.c0i * ar;
+        h[6 + r] = s[6 + r] + (T)k.c1r * br - (T)k.c1i * bi;
+        h[6 + i] = s[6 + i] + (T)k.c1r * bi + (T)k.c1i * br;
+    }
+}
+
+template <typename T>
+WCL_DEV void spin_accumulate_rt(const RtCoef& k, const T w[12], T f, T acc[24]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int r = 2 * c, i = 2 * c + 1;
+        const T w0r = w[r], w0i = w[i], w1r = w[6 + r], w1i = w[6 + i];
+        acc[r] += f * w0r;
+        acc[i] += f * w0i;
+        acc[6 + r] += f * w1r;
+        acc[6 + i] += f * w1i;
+        const T ar = k.p0 ? w1r : w0r, ai = k.p0 ? w1i : w0i;   // w_q0
+        const T br = k.p0 ? w0r : w1r, bi = k.p0 ? w0i : w1i;   // w_q1
+        acc[12 + r] += f * ((T)k.d0r * ar - (T)k.d0i * ai);
+        acc[12 + i] += f * ((T)k.d0r * ai + (T)k.d0i * ar);
+        acc[18 + r] += f * ((T)k.d1r * br - (T)k.d1i * bi);
+        acc[18 + i] += f * ((T)k.d1r * bi + (T)k.d1i * br);
+    }
+}
+
+// component mu of x[4] without dynamic register indexing
+WCL_DEV int pick(const int x[4], int mu) { return mu == 0 ? x[0] : mu == 1 ? x[1] : mu == 2 ? x[2] : x[3]; }
+WCL_DEV void put(int x[4], int mu, int v) {
+    x[0] = mu == 0 ? v : x[0];
+    x[1] = mu == 1 ? v : x[1];
+    x[2] = mu == 2 ? v : x[2];
+    x[3] = mu == 3 ? v : x[3];
+}

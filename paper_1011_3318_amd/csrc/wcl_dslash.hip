@@ -95,15 +95,216 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
     }
 }
 
+// ------------------------------------------------ several lanes per site
+// Clover block k of 36 reals (packed Hermitian 6x6).
+template <int P>
+struct CloverBlk;
+template <>
+struct CloverBlk<WCL_F64> {
+    WCL_DEV static void load(const void* base, int V, int i, int k, double c[36]) {
+        const d2v* p = (const d2v*)base + (size_t)18 * k * V;
+#pragma unroll
+        for (int q = 0; q < 18; ++q) {
+            d2v v = ld_nt(p + (size_t)q * V + i);
+            c[2 * q] = v.x;
+            c[2 * q + 1] = v.y;
+        }
+    }
+};
+template <>
+struct CloverBlk<WCL_F32> {
+    WCL_DEV static void load(const void* base, int V, int i, int k, float c[36]) {
+        const f4v* p = (const f4v*)base + (size_t)9 * k * V;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            f4v v = ld_nt(p + (size_t)q * V + i);
+            c[4 * q] = v.x;
+            c[4 * q + 1] = v.y;
+            c[4 * q + 2] = v.z;
+            c[4 * q + 3] = v.w;
+        }
+    }
+};
+template <>
+struct CloverBlk<WCL_F16> {
+    // block 0 = reals 0..35 (groups 0..4), block 1 = reals 36..71 (groups 4..8)
+    WCL_DEV static void load(const void* base, int V, int i, int k, float c[36]) {
+        const h8v* p = (const h8v*)base + (size_t)4 * k * V;
+        const float* sc = (const float*)((const char*)base + (((size_t)V * 144 + 255) / 256) * 256);
+        const float s = sc[i];
+        const int off = 4 * k;   // first real of the block inside group 4k
+        float t[40];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            f8v v = __builtin_convertvector(ld_nt(p + (size_t)q * V + i), f8v);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) t[8 * q + j] = v[j] * s;
+        }
+#pragma unroll
+        for (int j = 0; j < 36; ++j) c[j] = off ? t[4 + j] : t[j];
+    }
+};
+
+// Stores the float groups of s that belong to `lane` of LPS lanes.
+template <int P>
+struct SpinorPart;
+template <>
+struct SpinorPart<WCL_F64> {
+    template <int LPS>
+    WCL_DEV static void store(void* base, int V, int i, const double s[24], int lane) {
+        d2v* p = (d2v*)base;
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            if (k % LPS == lane) st_nt(p + (size_t)k * V + i, d2v{s[2 * k], s[2 * k + 1]});
+    }
+};
+template <>
+struct SpinorPart<WCL_F32> {
+    template <int LPS>
+    WCL_DEV static void store(void* base, int V, int i, const float s[24], int lane) {
+        f4v* p = (f4v*)base;
+#pragma unroll
+        for (int g = 0; g < 6; ++g)
+            if (g % LPS == lane) st_nt(p + (size_t)g * V + i, f4v{s[4 * g], s[4 * g + 1], s[4 * g + 2], s[4 * g + 3]});
+    }
+};
+template <>
+struct SpinorPart<WCL_F16> {
+    template <int LPS>
+    WCL_DEV static void store(void* base, int V, int i, const float s[24], int lane) {
+        float m = 0.f;
+#pragma unroll
+        for (int j = 0; j < 24; ++j) m = fmaxf(m, fabsf(s[j]));
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+        h8v* p = (h8v*)base;
+#pragma unroll
+        for (int g = 0; g < 3; ++g)
+            if (g % LPS == lane) {
+                f8v v;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = s[8 * g + j] * inv;
+                st_nt(p + (size_t)g * V + i, __builtin_convertvector(v, h8v));
+            }
+        if (lane == LPS - 1) st_nt((float*)((char*)base + (((size_t)48 * V + 255) / 256) * 256) + i, m);
+    }
+};
+
+// LPS lanes per site: lane j takes directions j*(4/LPS) .. and, for j < 2,
+// clover block j; the partial sums are added across the lanes with xor
+// shuffles (identical on every lane, so the result is deterministic).
+template <int GP, int SPI, int SPO, int EPI, int SPY, int LPS>
+__global__ __launch_bounds__(256) void k_dslash_ml(DslashArgs a) {
+    using T = typename Real<GP>::T;
+    static_assert((GP == WCL_F64) == (SPI == WCL_F64), "FP64 arithmetic needs FP64 spinors and links");
+    constexpr int SPW = 256 / LPS, DPL = 4 / LPS;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int rhs = lb % a.nrhs;
+    const int tile = lb / a.nrhs;
+    const int lane = threadIdx.x % LPS;
+    const int i = tile * SPW + threadIdx.x / LPS;
+    const bool active = i < a.g.V;
+    const int V = a.g.V;
+    T acc[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc[k] = T(0);
+    const char* in = (const char*)a.in + rhs * a.in_stride;
+    if (active) {
+        int x[4];
+        geom_coords(a.g, i, x);
+        if (lane < 2) {
+            T s[24], c[36], xs[12], y[12];
+            SpinorIO<SPI>::load(in, V, i, s);
+            CloverBlk<GP>::load(a.clover, V, i, lane, c);
+#pragma unroll
+            for (int j = 0; j < 12; ++j) xs[j] = lane ? s[12 + j] : s[j];
+            herm6_apply(c, xs, y);
+            const T ck = T(a.csw * a.kappa);
+#pragma unroll
+            for (int j = 0; j < 12; ++j) {
+                const T v = xs[j] + ck * y[j];
+                acc[j] = lane ? T(0) : v;
+                acc[12 + j] = lane ? v : T(0);
+            }
+        }
+        const T mk = T(-a.kappa);
+#pragma unroll
+        for (int m = 0; m < DPL; ++m) {
+            const int mu = lane * DPL + m;
+            const int xm = pick(x, mu), Lm = pick(a.g.L, mu);
+            const T bcm = T(pick(a.g.bc, mu));
+            T s[24], h[12], w[12], u[18];
+            {   // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
+                int y[4] = {x[0], x[1], x[2], x[3]};
+                const bool wrap = xm + 1 == Lm;
+                put(y, mu, wrap ? 0 : xm + 1);
+                SpinorIO<SPI>::load(in, V, geom_index(a.g, y), s);
+                const RtCoef kf = rt_coef(mu, true);
+                spin_project_rt(kf, s, h);
+                GaugeIO<GP>::load(a.gauge, V, mu, i, u);
+                su3_apply2<false>(u, h, w);
+                spin_accumulate_rt(kf, w, wrap ? mk * bcm : mk, acc);
+            }
+            {   // backward: (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)
+                int y[4] = {x[0], x[1], x[2], x[3]};
+                const bool wrap = xm == 0;
+                put(y, mu, wrap ? Lm - 1 : xm - 1);
+                const int jb = geom_index(a.g, y);
+                SpinorIO<SPI>::load(in, V, jb, s);
+                const RtCoef kb = rt_coef(mu, false);
+                spin_project_rt(kb, s, h);
+                GaugeIO<GP>::load(a.gauge, V, mu, jb, u);
+                su3_apply2<true>(u, h, w);
+                spin_accumulate_rt(kb, w, wrap ? mk * bcm : mk, acc);
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < LPS; off <<= 1)
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[k] += __shfl_xor(acc[k], off, 64);
+    if (active) {
+        if (EPI == DS_AXPY) {
+            T y[24];
+            SpinorIO<SPY>::load((const char*)a.y + rhs * a.y_stride, V, i, y);
+#pragma unroll
+            for (int k = 0; k < 24; ++k) acc[k] = y[k] - acc[k];
+        }
+        SpinorPart<SPO>::template store<LPS>((char*)a.out + rhs * a.out_stride, V, i, acc, lane);
+    }
+    if (EPI == DS_DOT) {
+        double d[3] = {0.0, 0.0, 0.0};
+        if (active && lane == 0) {
+            T v[24];
+            SpinorIO<SPO>::load((const char*)a.a + rhs * a.a_stride, V, i, v);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                T ar = v[2 * k], ai = v[2 * k + 1], br = acc[2 * k], bi = acc[2 * k + 1];
+                d[0] += (double)(ar * br + ai * bi);
+                d[1] += (double)(ar * bi - ai * br);
+                d[2] += (double)(br * br + bi * bi);
+            }
+        }
+        block_reduce3(d, a.partial + 3 * (size_t)(tile + (size_t)rhs * (gridDim.x / a.nrhs)));
+    }
+}
+
 template <int GP, int SPI, int SPO, int EPI, int SPY>
 static int launch_t(const DslashArgs& a, hipStream_t st) {
-    int tiles = (a.g.V + 255) / 256;
-    k_dslash<GP, SPI, SPO, EPI, SPY><<<tiles * a.nrhs, 256, 0, st>>>(a);
+    const int tiles = dslash_partials_per_rhs(a.g.V, a.lps);
+    switch (a.lps) {
+        case 2: k_dslash_ml<GP, SPI, SPO, EPI, SPY, 2><<<tiles * a.nrhs, 256, 0, st>>>(a); break;
+        case 4: k_dslash_ml<GP, SPI, SPO, EPI, SPY, 4><<<tiles * a.nrhs, 256, 0, st>>>(a); break;
+        default: k_dslash<GP, SPI, SPO, EPI, SPY><<<tiles * a.nrhs, 256, 0, st>>>(a); break;
+    }
     WCL_HIP(hipGetLastError());
     return WCL_OK;
 }
 
-int dslash_partials_per_rhs(int V) { return (V + 255) / 256; }
+// workgroups (= dot-product partial sums) per rhs for lps lanes per site
+int dslash_partials_per_rhs(int V, int lps) {
+    const int spw = 256 / (lps == 2 || lps == 4 ? lps : 1);
+    return (V + spw - 1) / spw;
+}
 
 // Runtime dispatch over the instantiated combinations.
 int launch_dslash(const DslashArgs& a, int gp, int spi, int spo, int epi, int spy, hipStream_t st) {

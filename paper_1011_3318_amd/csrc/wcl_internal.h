@@ -153,6 +153,7 @@ struct wcl_lattice {
     void* gauge[3] = {nullptr, nullptr, nullptr};   // indexed by WCL_F64/F32/F16
     void* clover[3] = {nullptr, nullptr, nullptr};
     Workspace* ws = nullptr;
+    int lps = 1;   // lanes per site of the full-lattice D-apply (tunable)
 };
 
 // device memory accounting against the context budget

@@ -16,6 +16,7 @@ struct DslashArgs {
     size_t in_stride, out_stride, y_stride, a_stride;  // bytes per rhs
     double kappa, csw;
     int nrhs;
+    int lps;             // lanes per site: 1, 2 or 4
     double* partial;     // DS_DOT: [nrhs][tiles][3]
 };
 
@@ -28,7 +29,7 @@ int launch_clover_build(const Geom& g, const void* g64, void* c64, void* c32, vo
 int launch_pack_clover(const Geom& g, const double* host_dev, void* c64, void* c32, void* c16, hipStream_t st);
 int launch_unpack_clover(const Geom& g, const void* c64, double* host_dev, hipStream_t st);
 
-int dslash_partials_per_rhs(int V);
+int dslash_partials_per_rhs(int V, int lps);
 int launch_dslash(const DslashArgs& a, int gp, int spi, int spo, int epi, int spy, hipStream_t st);
 
 // ------------------------------------------------------------- solvers --
@@ -82,5 +83,7 @@ int launch_blk_project(const BlockArgs& a, int src_prec, hipStream_t st);
 int launch_blk_dslash(const BlockArgs& a, int gp, hipStream_t st);
 int launch_blk_update(const BlockArgs& a, int vj_prec, int last, hipStream_t st);
 int launch_blk_unpack(const BlockArgs& a, const float* ws, double* out, hipStream_t st);
+int fused_threads(int ev);   // workgroup size of the fused domain solver, 0 if it does not fit
+int launch_blk_fused(const BlockArgs& a, int gp, int src_prec, hipStream_t st);
 int blas_restart(int prec, int64_t V, int nrhs, const Scal* sc, const void* src, void* r, void* rh, void* p, void* v,
                  hipStream_t st);

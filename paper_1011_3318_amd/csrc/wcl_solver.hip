@@ -148,11 +148,25 @@ static int need_fields(const wcl_lattice* lat) {
 }
 
 // ------------------------------------------------------------------ RAS --
-static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int storage, double kappa, double csw,
-                     const void* r, void* v, int nrhs, hipStream_t st, wcl_solve_stats* stats) {
+// The fused (on-chip) domain solver takes extended domains of up to 256
+// sites; larger ones use the split path.
+static int pick_kernel(const Blocks& B, int requested, bool* fused) {
+    const bool fits = fused_threads(B.ev) == 256;
+    if (requested == WCL_BLOCK_FUSED && !fits) {
+        wcl_set_error("fused domain solver needs an extended domain of at most 256 sites (got %d)", B.ev);
+        return WCL_EINVAL;
+    }
+    *fused = requested != WCL_BLOCK_SPLIT && fits;
+    return WCL_OK;
+}
+
+static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int storage, int kernel, double kappa,
+                     double csw, const void* r, void* v, int nrhs, hipStream_t st, wcl_solve_stats* stats) {
     const int64_t V = lat->V;
     const size_t s32 = spinor_rhs_bytes(WCL_F32, V), sst = spinor_rhs_bytes(storage, V);
-    const int NE = B.nblocks * B.ev, wpb = (B.ev + 255) / 256;
+    bool fused = false;
+    WCL_CHECK(pick_kernel(B, kernel, &fused));
+    const int NE = fused ? 0 : B.nblocks * B.ev, wpb = (B.ev + 255) / 256;
     BlockArgs a{};
     a.g = lat->g;
     a.B = B;
@@ -167,10 +181,10 @@ static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int stora
     a.out = v;
     a.out_stride = s32;
     const size_t wsb = (size_t)16 * 6 * NE * nrhs;
-    WCL_CHECK(ws->get("ras.rho", wsb, &a.rho));
-    WCL_CHECK(ws->get("ras.q", wsb, &a.q));
-    WCL_CHECK(ws->get("ras.x", wsb, &a.x));
-    WCL_CHECK(ws->get("ras.partial", (size_t)24 * nrhs * B.nblocks * wpb, (void**)&a.partial));
+    if (!fused) WCL_CHECK(ws->get("ras.rho", wsb, &a.rho));
+    if (!fused) WCL_CHECK(ws->get("ras.q", wsb, &a.q));
+    if (!fused) WCL_CHECK(ws->get("ras.x", wsb, &a.x));
+    if (!fused) WCL_CHECK(ws->get("ras.partial", (size_t)24 * nrhs * B.nblocks * wpb, (void**)&a.partial));
     void *vj = nullptr, *rbuf[2] = {nullptr, nullptr};
     if (B.n_ras > 1) {
         WCL_CHECK(ws->get("ras.vj", sst * nrhs, &vj));
@@ -187,10 +201,14 @@ static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int stora
         a.vj = last ? nullptr : vj;
         a.vj_stride = sst;
         // projection r_{Omega'} = P r, then N_dominv MR steps, then R + sum
-        WCL_CHECK(launch_blk_project(a, src_prec, st));
-        for (int k = 0; k < B.n_dominv; ++k) {
-            WCL_CHECK(launch_blk_dslash(a, storage, st));
-            WCL_CHECK(launch_blk_update(a, storage, k == B.n_dominv - 1, st));
+        if (fused) {
+            WCL_CHECK(launch_blk_fused(a, storage, src_prec, st));
+        } else {
+            WCL_CHECK(launch_blk_project(a, src_prec, st));
+            for (int k = 0; k < B.n_dominv; ++k) {
+                WCL_CHECK(launch_blk_dslash(a, storage, st));
+                WCL_CHECK(launch_blk_update(a, storage, k == B.n_dominv - 1, st));
+            }
         }
         if (!last) {
             // r_{j+1} = r_j - D v_j
@@ -207,6 +225,7 @@ static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int stora
             d.kappa = kappa;
             d.csw = csw;
             d.nrhs = nrhs;
+            d.lps = lat->lps;
             WCL_CHECK(launch_dslash(d, storage, storage, storage, DS_AXPY, src_prec, st));
             if (stats) stats->dslash_full += nrhs;
         }
@@ -252,7 +271,7 @@ struct Engine {
         V = lat->V;
         vb = spinor_rhs_bytes(P, V) * nrhs;
         Gb = blas_partials(P, V);
-        Gd = dslash_partials_per_rhs((int)V);
+        Gd = dslash_partials_per_rhs((int)V, lat->lps);
         auto name = [&](const char* n) { return tag + "." + n; };
         WCL_CHECK(ws->get(name("r"), vb, &r));
         WCL_CHECK(ws->get(name("rh"), vb, &rh));
@@ -283,6 +302,7 @@ struct Engine {
         x.kappa = kappa;
         x.csw = csw;
         x.nrhs = nrhs;
+        x.lps = lat->lps;
         x.partial = partial;
         if (stats) stats->dslash_full += nrhs;
         return launch_dslash(x, gp, P, P, DS_DOT, P, st);
@@ -300,6 +320,7 @@ struct Engine {
         a.kappa = kappa;
         a.csw = csw;
         a.nrhs = nrhs;
+        a.lps = lat->lps;
         if (stats) stats->dslash_full += nrhs;
         return launch_dslash(a, gp, P, P, DS_AXPY, P, st);
     }
@@ -528,7 +549,7 @@ int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, 
     WCL_CHECK(ws->get("nest.b32", v32, &b32));
     WCL_CHECK(ws->get("nest.y32", v32, &y32));
     Precond Kras = [&](const void* in, void* out, Scal*, const std::vector<int>&) -> int {
-        return ras_apply(lat, ws, B, storage, kappa, csw, in, out, nrhs, st, S);
+        return ras_apply(lat, ws, B, storage, prm->ras.kernel, kappa, csw, in, out, nrhs, st, S);
     };
     Engine outer{lat, ws, "out", WCL_F64, WCL_F64, nrhs, kappa, csw, st, S};
     int outer_partials_G = blas_partials(WCL_F64, lat->V);
@@ -630,7 +651,7 @@ int wcl_ras_precondition(wcl_lattice* lat, const wcl_ras_params* ras, double kap
     Blocks B;
     WCL_CHECK(make_blocks(lat, ras, &B));
     WCL_HIP(hipSetDevice(lat->ctx->device));
-    return ras_apply(lat, lattice_ws(lat), B, ras->storage, kappa, csw, r_dev, v_dev, nrhs, (hipStream_t)stream,
+    return ras_apply(lat, lattice_ws(lat), B, ras->storage, ras->kernel, kappa, csw, r_dev, v_dev, nrhs, (hipStream_t)stream,
                      nullptr);
 }
 

@@ -59,16 +59,21 @@ def test_domain_operator(W, ctx, dims, block, s, storage):
     lat.close()
 
 
+RAS_CASES = [
+    ((8, 8, 8, 8), (4, 4, 4, 4), 0, 3, 4),     # fused (ev = 256)
+    ((8, 8, 8, 8), (2, 2, 2, 2), 1, 3, 4),     # fused, overlap (ev = 256)
+    ((4, 4, 4, 8), (4, 4, 4, 2), 1, 2, 3),     # fused, domain spans x, y, z (periodic inside)
+    ((8, 8, 8, 8), (4, 4, 4, 4), 1, 3, 4),     # split (ev = 1296)
+    ((8, 4, 6, 4), (4, 2, 2, 4), 1, 2, 5),     # split
+    ((16, 8, 8, 8), (8, 8, 8, 8), 1, 1, 3),    # split, the 8^4 domains of the 16^3x32 benchmark
+]
+
+
 @pytest.mark.parametrize("storage,tol", [(1, 1e-4), (2, 2e-2)])
-@pytest.mark.parametrize("dims,block,s,n_ras,nd", [
-    ((8, 8, 8, 8), (4, 4, 4, 4), 0, 3, 4),
-    ((8, 8, 8, 8), (4, 4, 4, 4), 1, 3, 4),
-    ((8, 4, 6, 4), (4, 2, 2, 4), 1, 2, 5),
-    ((16, 8, 8, 8), (8, 8, 8, 8), 1, 1, 3),
-])
+@pytest.mark.parametrize("dims,block,s,n_ras,nd", RAS_CASES)
 def test_ras_precondition(W, ctx, dims, block, s, n_ras, nd, storage, tol):
-    U, lat = make(W, ctx, dims)
-    o = Oracle(dims, U)
+    U, lat = make(W, ctx, dims, bc=(1, 1, 1, -1))
+    o = Oracle(dims, U, bc=(1, 1, 1, -1))
     r = I.gaussian_source(dims, 6)
     ras = W.RasParams.make(block=block, s=s, n_ras=n_ras, n_dominv=nd, storage=storage)
     rd = lat.pack(r, W.F32)
@@ -79,14 +84,31 @@ def test_ras_precondition(W, ctx, dims, block, s, n_ras, nd, storage, tol):
     e = rel_err(got, ref)
     print(f"RAS rel err {e:.2e}")
     assert e <= tol
+    # the split path computes the same operator
+    ras_split = W.RasParams.make(block=block, s=s, n_ras=n_ras, n_dominv=nd, storage=storage,
+                                 kernel=W.BLOCK_SPLIT)
+    v2 = lat.empty(W.F32)
+    lat.ras_precondition(ras_split, 0.124, 1.0, rd, v2)
+    assert rel_err(lat.unpack(v2, W.F32), got) <= (1e-5 if storage == 1 else 5e-3)
     lat.close()
 
 
-def test_ras_multi_rhs_equals_single(W, ctx):
+def test_ras_fused_rejects_large_domains(W, ctx):
+    dims = (8, 8, 8, 8)
+    _, lat = make(W, ctx, dims)
+    ras = W.RasParams.make(block=(4, 4, 4, 4), s=1, kernel=W.BLOCK_FUSED)
+    with pytest.raises(W.WclError) as e:
+        lat.ras_precondition(ras, 0.12, 1.0, lat.zeros(W.F32), lat.empty(W.F32))
+    assert e.value.code == W.EINVAL
+    lat.close()
+
+
+@pytest.mark.parametrize("s", [0, 1])
+def test_ras_multi_rhs_equals_single(W, ctx, s):
     dims = (8, 8, 8, 8)
     U, lat = make(W, ctx, dims)
     r = I.gaussian_source(dims, 8, nrhs=3)
-    ras = W.RasParams.make(block=(4, 4, 4, 4), s=1, n_ras=3, n_dominv=4)
+    ras = W.RasParams.make(block=(4, 4, 4, 4), s=s, n_ras=3, n_dominv=4)
     v = lat.empty(W.F32, 3)
     lat.ras_precondition(ras, 0.12, 1.0, lat.pack(r, W.F32, 3), v, nrhs=3)
     many = lat.unpack(v, W.F32, 3)
