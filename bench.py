@@ -37,6 +37,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--overlap", type=int, default=0, help="RAS overlap s (depth d = 2s)")
+    ap.add_argument("--block", default="8x8x8x8", help="RAS domain shape, e.g. 8x8x8x8 or 4x4x4x4")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16"], help="RAS storage precision")
+    ap.add_argument("--n-dominv", type=int, default=4)
+    ap.add_argument("--n-ras", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dapply", action="store_true")
     ap.add_argument("--mode", default="full", choices=["full", "dapply", "copyref"],
@@ -131,7 +135,9 @@ def main():
         return
     dims = (16, 16, 16, 32)
     kappa, csw, tol = 0.125, 1.0, 1e-10
-    block, s, nd, nras = (8, 8, 8, 8), args.overlap, 4, 3
+    block = tuple(int(v) for v in args.block.split("x"))
+    s, nd, nras = args.overlap, args.n_dominv, args.n_ras
+    storage = W.F16 if args.storage == "f16" else W.F32
     ctx = W.Context(0)
     lat = W.Lattice(ctx, dims)
     U = I.random_gauge(dims, 0.5, 1)
@@ -140,7 +146,7 @@ def main():
     e = lat.pack(eta, W.F64)
     phi = lat.zeros(W.F64)
     params = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=100,
-                                 ras=W.RasParams.make(block=block, s=s, n_ras=nras, n_dominv=nd, storage=W.F32))
+                                 ras=W.RasParams.make(block=block, s=s, n_ras=nras, n_dominv=nd, storage=storage))
 
     # ---- nested RAS solve: warmup, then exactly K timed steps
     for _ in range(args.warmup):
@@ -218,7 +224,7 @@ def main():
         "data": "synthetic (seeded random SU(3) gauge field and Gaussian source)",
         "config": {"workload": "16^3x32 nested RAS-BiCGStab solve to 1e-10",
                    "lattice": list(dims), "eps": 0.5, "kappa": kappa, "csw": csw, "rhs": 1,
-                   "ras": {"block": list(block), "s": s, "n_dominv": nd, "n_ras": nras, "storage": "f32"},
+                   "ras": {"block": list(block), "s": s, "n_dominv": nd, "n_ras": nras, "storage": args.storage},
                    "parallelism": "single GPU"},
         "time_to_solution_ms": round(ms_per_step, 3),
         "true_residual": true_res,

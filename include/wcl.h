@@ -204,6 +204,66 @@ int wcl_solve_nested_bicgstab(wcl_lattice* lat, const wcl_solver_params* p, doub
 int wcl_solve_bicgstab_f64(wcl_lattice* lat, double tol, int max_iter, double kappa, double csw, const void* eta_dev,
                            void* phi_dev, wcl_solve_stats* stats, void* stream);
 
+/* ---- autotuner ----
+ * Picks the RAS parameters the paper leaves to tuning (Sec. 2: overlap
+ * depth, N_dominv, NRAS; Sec. 5 scans them by hand) plus the domain shape,
+ * storage precision, inner tolerance and the D-apply's lanes per site, by
+ * timing complete nested solves of eta on this lattice: stage 1 scans
+ * domain shape {4^4, 4^3x8, 8^4} x overlap {0, 1} x storage {FP32, FP16};
+ * stage 2 scans N_dominv {2, 4, 6} x NRAS {1, 2, 3}; stage 3 the inner
+ * tolerance {1e-2, 1e-3, 1e-4} and lanes per site {1, 2}.  Candidates that
+ * do not converge are skipped.  With cache_path != NULL the result is read
+ * from / appended to that JSON-lines file, keyed by device architecture,
+ * dims, nrhs, kappa and c_sw.  *best receives the chosen parameters (tol_outer,
+ * max_* and max_restarts are copied from *base), *best_ms its solve time;
+ * the lattice keeps the chosen lanes per site.  Blocks until done. */
+int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, double kappa, double csw, const void* eta_dev,
+                 int nrhs, const char* cache_path, wcl_solver_params* best, double* best_ms, void* stream);
+
+/* ---- serving (continuous batching of solve requests) ----
+ * A server owns resident gauge/clover fields per registered configuration and
+ * max_slots worker slots, each with its own HIP stream and solver workspace.
+ * Requests wait in FIFO order and are admitted as soon as a slot is free and
+ * the HBM they need fits the budget; admitted requests run concurrently on
+ * the device.  Each result is identical (bitwise) to the same solve run
+ * alone: a solve's arithmetic does not depend on the other requests.
+ * wcl_submit and wcl_poll are thread-safe. */
+typedef struct wcl_server_params {
+    uint64_t hbm_budget_bytes;  /* total for fields + workspaces; 0 = the context budget */
+    int max_slots;              /* concurrent solves (>= 1) */
+    int max_queue;              /* waiting requests before WCL_ENOMEM (0 = 4096) */
+} wcl_server_params;
+
+typedef struct wcl_request {
+    uint64_t config_id;         /* registered gauge configuration */
+    double kappa, csw;
+    const wcl_solver_params* params;  /* NULL = defaults (tol 1e-10, RAS 4^4 domains, FP16 storage) */
+    const double* eta_host;     /* host spinor layout, 1 rhs; must stay valid until done */
+    double* phi_host;           /* receives the solution; must stay valid until done */
+} wcl_request;
+
+typedef struct wcl_result {
+    int status;                 /* WCL_OK or the solver's error code */
+    wcl_solve_stats stats;
+    double t_submit, t_admit, t_done;   /* seconds, steady clock */
+} wcl_result;
+
+int wcl_server_create(wcl_ctx* ctx, const wcl_server_params* p, wcl_server** srv);
+/* Waits for every admitted and queued request, then frees everything. */
+int wcl_server_destroy(wcl_server* srv);
+/* Uploads U (host gauge layout) for config_id and builds its clover field;
+ * they stay resident until the server is destroyed.  Synchronous. */
+int wcl_register_gauge(wcl_server* srv, uint64_t config_id, const int dims[4], const double* U_host);
+/* Queues a request; *ticket identifies it.  WCL_EINVAL for an unknown
+ * config or bad parameters; WCL_ENOMEM if the request can never fit the
+ * budget or the queue is full (other requests are unaffected). */
+int wcl_submit(wcl_server* srv, const wcl_request* req, uint64_t* ticket);
+/* WCL_PENDING while queued or running; otherwise fills *res, returns WCL_OK
+ * and forgets the ticket. */
+int wcl_poll(wcl_server* srv, uint64_t ticket, wcl_result* res);
+/* Blocks until the ticket is done, then behaves like wcl_poll. */
+int wcl_wait(wcl_server* srv, uint64_t ticket, wcl_result* res);
+
 #ifdef __cplusplus
 }
 #endif

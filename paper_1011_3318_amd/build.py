@@ -16,8 +16,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
-BUILD = os.path.join(HERE, "_build")
-LIB = os.path.join(HERE, "libwcl.so")
+BUILD = os.environ.get("WCL_BUILD_DIR", os.path.join(HERE, "_build"))
+LIB = os.environ.get("WCL_LIB_OUT", os.path.join(HERE, "libwcl.so"))
 ARCH = os.environ.get("WCL_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -26,7 +26,7 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-ffp-contract=fast", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     f"-I{INCLUDE}", f"-I{CSRC}",
-]
+] + os.environ.get("WCL_HIPCC_EXTRA", "").split()
 
 
 def _torch_lib_dir() -> str:

@@ -21,25 +21,32 @@ void wcl_set_error(const char* fmt, ...) {
 int wcl_dev_alloc(wcl_ctx* ctx, void** p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) return WCL_OK;
-    if (ctx->in_use + bytes > ctx->budget) {
-        wcl_set_error("HBM budget exhausted: %llu in use + %llu requested > %llu budget",
-                      (unsigned long long)ctx->in_use, (unsigned long long)bytes, (unsigned long long)ctx->budget);
-        return WCL_ENOMEM;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        if (ctx->in_use + bytes > ctx->budget) {
+            wcl_set_error("HBM budget exhausted: %llu in use + %llu requested > %llu budget",
+                          (unsigned long long)ctx->in_use, (unsigned long long)bytes,
+                          (unsigned long long)ctx->budget);
+            return WCL_ENOMEM;
+        }
+        ctx->in_use += bytes;
     }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         *p = nullptr;
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->in_use -= bytes;
         wcl_set_error("hipMalloc(%llu) failed: %s", (unsigned long long)bytes, hipGetErrorString(e));
         return WCL_ENOMEM;
     }
-    ctx->in_use += bytes;
     return WCL_OK;
 }
 
 void wcl_dev_free(wcl_ctx* ctx, void* p, size_t bytes) {
     if (!p) return;
     (void)hipFree(p);
+    std::lock_guard<std::mutex> g(ctx->mu);
     ctx->in_use -= bytes;
 }
 

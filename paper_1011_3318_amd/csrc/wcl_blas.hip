@@ -54,9 +54,11 @@ WCL_DEV void dot_acc(f4v a, f4v b, double d[3]) {
 }
 
 struct BlasGrid {
-    int n;        // elements per rhs
+    int n;        // elements per rhs (whole tiles)
     int stride;   // elements between rhs
     int G;        // workgroups per rhs
+    int last;     // first element of the last tile
+    int rem;      // sites used in the last tile (64 when the volume fills it)
 };
 
 #define BLAS_PROLOGUE                                   \
@@ -64,6 +66,11 @@ struct BlasGrid {
     const int wg = blockIdx.x % bg.G;                   \
     const size_t base = (size_t)rhs * bg.stride;        \
     const int step = bg.G * 256;
+
+// loop over the elements of one rhs, skipping the padding of the last tile
+#define BLAS_FOR(k)                                                    \
+    for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step)          \
+        if (k < bg.last || (k & 63) < bg.rem)
 
 // p = r + beta (p - omega v), beta = (rho/rho_old)(alpha/omega); partial |p|^2
 template <int P>
@@ -82,7 +89,7 @@ __global__ __launch_bounds__(256) void k_p_update(BlasGrid bg, const Scal* sc, c
         const E* r = (const E*)r_ + base;
         E* p = (E*)p_ + base;
         const E* v = (const E*)v_ + base;
-        for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step) {
+        BLAS_FOR(k) {
             E pv = p[k] - cm(wr, wi, v[k]);
             E np = r[k] + cm(br, bi, pv);
             p[k] = np;
@@ -104,7 +111,7 @@ __global__ __launch_bounds__(256) void k_s_update(BlasGrid bg, const Scal* sc, c
     const E* r = (const E*)r_ + base;
     const E* v = (const E*)v_ + base;
     E* s = (E*)s_ + base;
-    for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step) s[k] = r[k] - cm(ar, ai, v[k]);
+    BLAS_FOR(k) s[k] = r[k] - cm(ar, ai, v[k]);
 }
 
 // x += alpha p^ + omega s^;  r = s - omega t;  partials <rhat, r>, |r|^2
@@ -125,7 +132,7 @@ __global__ __launch_bounds__(256) void k_xr_update(BlasGrid bg, const Scal* sc, 
         const E* t = (const E*)t_ + base;
         E* r = (E*)r_ + base;
         const E* rh = (const E*)rh_ + base;
-        for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step) {
+        BLAS_FOR(k) {
             x[k] = x[k] + cm(ar, ai, ph[k]) + cm(wr, wi, sh[k]);
             E nr = s[k] - cm(wr, wi, t[k]);
             r[k] = nr;
@@ -145,7 +152,7 @@ __global__ __launch_bounds__(256) void k_dot(BlasGrid bg, const Scal* sc, const 
     if (!sc || sc[rhs].active) {
         const E* a = (const E*)a_ + base;
         const E* b = (const E*)b_ + base;
-        for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step) dot_acc(a[k], b[k], d);
+        BLAS_FOR(k) dot_acc(a[k], b[k], d);
     }
     block_reduce3(d, partial + 3 * ((size_t)rhs * bg.G + wg));
 }
@@ -158,9 +165,9 @@ __global__ __launch_bounds__(256) void k_copy(BlasGrid bg, const void* a_, void*
     E* y = (E*)y_ + base;
     if (a_) {
         const E* a = (const E*)a_ + base;
-        for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step) y[k] = a[k];
+        BLAS_FOR(k) y[k] = a[k];
     } else {
-        for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step) y[k] = E{};
+        BLAS_FOR(k) y[k] = E{};
     }
 }
 
@@ -174,10 +181,11 @@ __global__ __launch_bounds__(256) void k_to_f32_scaled(int V, int G, const Scal*
     const double f = sc[rhs].pp > 0 ? 1.0 / sqrt(sc[rhs].pp) : 0.0;
     const d2v* a = (const d2v*)a_ + (size_t)rhs * astride2;
     f4v* y = (f4v*)y_ + (size_t)rhs * ystride4;
-    const int n = 6 * V;
+    const int n = 6 * ((V + 63) / 64 * 64);
     for (int k = wg * 256 + threadIdx.x; k < n; k += G * 256) {
-        const int g = k / V, i = k - g * V;
-        d2v u = a[(size_t)(2 * g) * V + i], w = a[(size_t)(2 * g + 1) * V + i];
+        const int i = (k / 384) * 64 + (k & 63), g = (k >> 6) % 6;
+        if (i >= V) continue;
+        d2v u = a[tix(2 * g, i, 12)], w = a[tix(2 * g + 1, i, 12)];
         y[k] = f4v{(float)(u.x * f), (float)(u.y * f), (float)(w.x * f), (float)(w.y * f)};
     }
 }
@@ -189,12 +197,13 @@ __global__ __launch_bounds__(256) void k_to_f64_scaled(int V, int G, const Scal*
     const double f = sqrt(sc[rhs].pp);
     const f4v* a = (const f4v*)a_ + (size_t)rhs * astride4;
     d2v* y = (d2v*)y_ + (size_t)rhs * ystride2;
-    const int n = 6 * V;
+    const int n = 6 * ((V + 63) / 64 * 64);
     for (int k = wg * 256 + threadIdx.x; k < n; k += G * 256) {
-        const int g = k / V, i = k - g * V;
+        const int i = (k / 384) * 64 + (k & 63), g = (k >> 6) % 6;
+        if (i >= V) continue;
         f4v v = a[k];
-        y[(size_t)(2 * g) * V + i] = d2v{(double)v.x * f, (double)v.y * f};
-        y[(size_t)(2 * g + 1) * V + i] = d2v{(double)v.z * f, (double)v.w * f};
+        y[tix(2 * g, i, 12)] = d2v{(double)v.x * f, (double)v.y * f};
+        y[tix(2 * g + 1, i, 12)] = d2v{(double)v.z * f, (double)v.w * f};
     }
 }
 
@@ -255,9 +264,13 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partial, int G, 
 // ------------------------------------------------------------ launchers --
 static BlasGrid blas_grid(int prec, int64_t V) {
     BlasGrid bg;
-    bg.n = (int)(V * (prec == WCL_F64 ? 12 : 6));
+    const int nc = prec == WCL_F64 ? 12 : 6;
+    const int64_t tiles = (V + 63) / 64;
+    bg.n = (int)(tiles * 64 * nc);
     bg.stride = (int)(spinor_rhs_bytes(prec, V) / 16);
     bg.G = (int)std::min<int64_t>((bg.n + 255) / 256, 1024);
+    bg.last = (int)((tiles - 1) * 64 * nc);
+    bg.rem = (int)(V - (tiles - 1) * 64);
     return bg;
 }
 
@@ -330,7 +343,7 @@ __global__ __launch_bounds__(256) void k_restart(BlasGrid bg, const Scal* sc, co
     E* p = (E*)p_ + base;
     E* v = (E*)v_ + base;
     const E* src = src_ ? (const E*)src_ + base : nullptr;
-    for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step) {
+    BLAS_FOR(k) {
         E rv = src ? src[k] : r[k];
         r[k] = rv;
         rh[k] = rv;

@@ -440,12 +440,10 @@ int fused_threads(int ev) { return ev <= 256 ? 256 : (ev <= 512 ? 512 : 0); }
 template <int GP, int SRC, int VP, int NT>
 static int launch_fused_t(const BlockArgs& a, hipStream_t st) {
     const size_t lds = (size_t)72 * NT * sizeof(float);
-    static bool attr = false;   // dynamic LDS above the 64 KB default
-    if (!attr) {
-        WCL_HIP(hipFuncSetAttribute((const void*)k_blk_fused<GP, SRC, VP, NT>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr = true;
-    }
+    // dynamic LDS above the 64 KB default; set once per instantiation (thread-safe static)
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_blk_fused<GP, SRC, VP, NT>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    WCL_HIP(attr);
     k_blk_fused<GP, SRC, VP, NT><<<a.B.nblocks * a.nrhs, NT, lds, st>>>(a, a.vj != nullptr);
     WCL_HIP(hipGetLastError());
     return WCL_OK;

@@ -24,13 +24,30 @@ struct Real<WCL_F64> {
 
 // Non-temporal loads for data streamed exactly once per launch (links,
 // clover); neighbour-shared spinor data uses ordinary cached loads.
+#ifndef WCL_NT_LOADS
+#define WCL_NT_LOADS 1
+#endif
+#ifndef WCL_NT_STORES
+#define WCL_NT_STORES 1
+#endif
+#ifndef WCL_XCD_REMAP
+#define WCL_XCD_REMAP 1
+#endif
 template <typename V>
 WCL_DEV V ld_nt(const V* p) {
+#if WCL_NT_LOADS
     return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
 }
 template <typename V>
 WCL_DEV void st_nt(V* p, V v) {
+#if WCL_NT_STORES
     __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
 }
 
 // ------------------------------------------------------------ spinors ---
@@ -45,7 +62,7 @@ struct SpinorIO<WCL_F64> {
         const d2v* p = (const d2v*)base;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            d2v v = p[(size_t)k * V + i];
+            d2v v = p[tix(k, i, 12)];
             s[2 * k] = v.x;
             s[2 * k + 1] = v.y;
         }
@@ -55,7 +72,7 @@ struct SpinorIO<WCL_F64> {
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             d2v v = {s[2 * k], s[2 * k + 1]};
-            st_nt(p + (size_t)k * V + i, v);
+            st_nt(p + tix(k, i, 12), v);
         }
     }
 };
@@ -67,7 +84,7 @@ struct SpinorIO<WCL_F32> {
         const f4v* p = (const f4v*)base;
 #pragma unroll
         for (int g = 0; g < 6; ++g) {
-            f4v v = p[(size_t)g * V + i];
+            f4v v = p[tix(g, i, 6)];
             s[4 * g] = v.x;
             s[4 * g + 1] = v.y;
             s[4 * g + 2] = v.z;
@@ -79,7 +96,7 @@ struct SpinorIO<WCL_F32> {
 #pragma unroll
         for (int g = 0; g < 6; ++g) {
             f4v v = {s[4 * g], s[4 * g + 1], s[4 * g + 2], s[4 * g + 3]};
-            st_nt(p + (size_t)g * V + i, v);
+            st_nt(p + tix(g, i, 6), v);
         }
     }
 };
@@ -90,15 +107,14 @@ template <>
 struct SpinorIO<WCL_F16> {
     using T = float;
     WCL_DEV static const float* scale_ptr(const void* base, int V) {
-        return (const float*)((const char*)base + round_up_dev(48 * (size_t)V, 256));
+        return (const float*)((const char*)base + half_spinor_scale_offset(V));
     }
-    WCL_DEV static size_t round_up_dev(size_t n, size_t a) { return (n + a - 1) / a * a; }
     WCL_DEV static void load(const void* base, int V, int i, T s[24]) {
         const h8v* p = (const h8v*)base;
         float sc = scale_ptr(base, V)[i];
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
-            f8v v = __builtin_convertvector(p[(size_t)g * V + i], f8v);
+            f8v v = __builtin_convertvector(p[tix(g, i, 3)], f8v);
 #pragma unroll
             for (int j = 0; j < 8; ++j) s[8 * g + j] = v[j] * sc;
         }
@@ -114,7 +130,7 @@ struct SpinorIO<WCL_F16> {
             f8v v;
 #pragma unroll
             for (int j = 0; j < 8; ++j) v[j] = s[8 * g + j] * inv;
-            st_nt(p + (size_t)g * V + i, __builtin_convertvector(v, h8v));
+            st_nt(p + tix(g, i, 3), __builtin_convertvector(v, h8v));
         }
         st_nt((float*)scale_ptr(base, V) + i, m);
     }
@@ -146,14 +162,18 @@ struct GaugeIO;
 template <>
 struct GaugeIO<WCL_F64> {
     using T = double;
-    WCL_DEV static void load(const void* base, int V, int mu, int i, T u[18]) {
-        const d2v* p = (const d2v*)base + (size_t)mu * 6 * V;
+    // rows 0,1 only (u[0..11]); row 2 is rebuilt by load() or by the caller
+    WCL_DEV static void load_raw(const void* base, int V, int mu, int i, T u[18]) {
+        const d2v* p = (const d2v*)base;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            d2v v = ld_nt(p + (size_t)k * V + i);
+            d2v v = ld_nt(p + tix(6 * mu + k, i, 24));
             u[2 * k] = v.x;
             u[2 * k + 1] = v.y;
         }
+    }
+    WCL_DEV static void load(const void* base, int V, int mu, int i, T u[18]) {
+        load_raw(base, V, mu, i, u);
         reconstruct_row2(u);
     }
 };
@@ -161,16 +181,20 @@ struct GaugeIO<WCL_F64> {
 template <>
 struct GaugeIO<WCL_F32> {
     using T = float;
-    WCL_DEV static void load(const void* base, int V, int mu, int i, T u[18]) {
-        const f4v* p = (const f4v*)base + (size_t)mu * 3 * V;
+    // rows 0,1 only (u[0..11]); row 2 is rebuilt by load() or by the caller
+    WCL_DEV static void load_raw(const void* base, int V, int mu, int i, T u[18]) {
+        const f4v* p = (const f4v*)base;
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
-            f4v v = ld_nt(p + (size_t)g * V + i);
+            f4v v = ld_nt(p + tix(3 * mu + g, i, 12));
             u[4 * g] = v.x;
             u[4 * g + 1] = v.y;
             u[4 * g + 2] = v.z;
             u[4 * g + 3] = v.w;
         }
+    }
+    WCL_DEV static void load(const void* base, int V, int mu, int i, T u[18]) {
+        load_raw(base, V, mu, i, u);
         reconstruct_row2(u);
     }
 };
@@ -178,16 +202,20 @@ struct GaugeIO<WCL_F32> {
 template <>
 struct GaugeIO<WCL_F16> {
     using T = float;
-    WCL_DEV static void load(const void* base, int V, int mu, int i, T u[18]) {
-        const h4v* p = (const h4v*)base + (size_t)mu * 3 * V;
+    // rows 0,1 only (u[0..11]); row 2 is rebuilt by load() or by the caller
+    WCL_DEV static void load_raw(const void* base, int V, int mu, int i, T u[18]) {
+        const h4v* p = (const h4v*)base;
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
-            f4v v = __builtin_convertvector(ld_nt(p + (size_t)g * V + i), f4v);
+            f4v v = __builtin_convertvector(ld_nt(p + tix(3 * mu + g, i, 12)), f4v);
             u[4 * g] = v.x;
             u[4 * g + 1] = v.y;
             u[4 * g + 2] = v.z;
             u[4 * g + 3] = v.w;
         }
+    }
+    WCL_DEV static void load(const void* base, int V, int mu, int i, T u[18]) {
+        load_raw(base, V, mu, i, u);
         reconstruct_row2(u);
     }
 };
@@ -205,7 +233,7 @@ struct CloverIO<WCL_F64> {
         const d2v* p = (const d2v*)base;
 #pragma unroll
         for (int k = 0; k < 36; ++k) {
-            d2v v = ld_nt(p + (size_t)k * V + i);
+            d2v v = ld_nt(p + tix(k, i, 36));
             c[2 * k] = v.x;
             c[2 * k + 1] = v.y;
         }
@@ -219,7 +247,7 @@ struct CloverIO<WCL_F32> {
         const f4v* p = (const f4v*)base;
 #pragma unroll
         for (int k = 0; k < 18; ++k) {
-            f4v v = ld_nt(p + (size_t)k * V + i);
+            f4v v = ld_nt(p + tix(k, i, 18));
             c[4 * k] = v.x;
             c[4 * k + 1] = v.y;
             c[4 * k + 2] = v.z;
@@ -233,11 +261,11 @@ struct CloverIO<WCL_F16> {
     using T = float;
     WCL_DEV static void load(const void* base, int V, int i, T c[72]) {
         const h8v* p = (const h8v*)base;
-        const float* sc = (const float*)((const char*)base + (((size_t)V * 144 + 255) / 256) * 256);
+        const float* sc = (const float*)((const char*)base + half_clover_scale_offset(V));
         float s = sc[i];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            f8v v = __builtin_convertvector(ld_nt(p + (size_t)k * V + i), f8v);
+            f8v v = __builtin_convertvector(ld_nt(p + tix(k, i, 9)), f8v);
 #pragma unroll
             for (int j = 0; j < 8; ++j) c[8 * k + j] = v[j] * s;
         }
@@ -380,6 +408,7 @@ WCL_DEV void clover_term(const T c[72], const T s[24], T ck, T acc[24]) {
 // each XCD walks a contiguous range of logical workgroup ids (and thereby a
 // contiguous piece of the column-ordered lattice in its own L2).
 WCL_DEV int xcd_remap(int b, int n) {
+    if (!WCL_XCD_REMAP) return b;
     const int nx = 8;
     int xcd = b % nx, k = b / nx;
     int q = n / nx, r = n % nx;

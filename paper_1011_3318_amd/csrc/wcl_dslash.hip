@@ -9,57 +9,80 @@
 #include "wcl_device.h"
 #include "wcl_kernels.h"
 
-template <int MU, bool FWD, int GP, int SPI, typename T>
-WCL_DEV void hop(const DslashArgs& a, const char* in, int j, int ulink_site, T f, T acc[24]) {
-    T s[24], h[12], w[12], u[18];
-    SpinorIO<SPI>::load(in, a.g.V, j, s);
+// One hop from already-loaded data: s = neighbour spinor, u = rows 0,1 of
+// the link (row 2 rebuilt here).  Forward: (1 - gamma_mu) U_mu(x) psi(x+mu);
+// backward: (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu).
+template <int MU, bool FWD, typename T>
+WCL_DEV void hop_compute(const T s[24], T u[18], T f, T acc[24]) {
+    T h[12], w[12];
+    reconstruct_row2(u);
     spin_project<MU, FWD>(s, h);
-    GaugeIO<GP>::load(a.gauge, a.g.V, MU, ulink_site, u);
     su3_apply2<!FWD>(u, h, w);
     spin_accumulate<MU, FWD>(w, f, acc);
 }
 
-template <int MU, int GP, int SPI, typename T>
-WCL_DEV void hops_dir(const DslashArgs& a, const char* in, int i, const int x[4], T mk, T acc[24]) {
-    int y[4] = {x[0], x[1], x[2], x[3]};
-    // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
-    T ph = T(1);
-    y[MU] = x[MU] + 1;
-    if (y[MU] == a.g.L[MU]) {
-        y[MU] = 0;
-        ph = T(a.g.bc[MU]);
+// The eight hops in the order (x+, x-, y+, y-, z+, z-, t+, t-): neighbour
+// site, link site and boundary phase of each.
+template <typename T>
+WCL_DEV void hop_sites(const Geom& g, int i, const int x[4], int nbr[8], int lnk[8], T ph[8]) {
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        const bool wf = x[mu] + 1 == g.L[mu];
+        y[mu] = wf ? 0 : x[mu] + 1;
+        nbr[2 * mu] = geom_index(g, y);
+        lnk[2 * mu] = i;
+        ph[2 * mu] = wf ? T(g.bc[mu]) : T(1);
+        const bool wb = x[mu] == 0;
+        y[mu] = wb ? g.L[mu] - 1 : x[mu] - 1;
+        nbr[2 * mu + 1] = geom_index(g, y);
+        lnk[2 * mu + 1] = nbr[2 * mu + 1];
+        ph[2 * mu + 1] = wb ? T(g.bc[mu]) : T(1);
     }
-    hop<MU, true, GP, SPI>(a, in, geom_index(a.g, y), i, mk * ph, acc);
-    // backward: (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)
-    ph = T(1);
-    y[MU] = x[MU] - 1;
-    if (y[MU] < 0) {
-        y[MU] = a.g.L[MU] - 1;
-        ph = T(a.g.bc[MU]);
-    }
-    int jb = geom_index(a.g, y);
-    hop<MU, false, GP, SPI>(a, in, jb, jb, mk * ph, acc);
 }
 
+// (D psi)(x).  Software-pipelined: the neighbour spinor and link of hop k+1
+// are requested before hop k is computed (two register buffers), so every
+// wavefront keeps two hops' loads in flight.
 template <int GP, int SPI, typename T>
 WCL_DEV void dslash_site(const DslashArgs& a, const char* in, int i, T acc[24]) {
-    int x[4];
+    const int V = a.g.V;
+    int x[4], nbr[8], lnk[8];
+    T ph[8];
     geom_coords(a.g, i, x);
+    hop_sites(a.g, i, x, nbr, lnk, ph);
+    T s0[24], u0[18], s1[24], u1[18];
+    SpinorIO<SPI>::load(in, V, nbr[0], s0);
+    GaugeIO<GP>::load_raw(a.gauge, V, 0, lnk[0], u0);
     {
         T s[24], c[72];
-        SpinorIO<SPI>::load(in, a.g.V, i, s);
-        CloverIO<GP>::load(a.clover, a.g.V, i, c);
+        SpinorIO<SPI>::load(in, V, i, s);
+        CloverIO<GP>::load(a.clover, V, i, c);
         clover_term(c, s, T(a.csw * a.kappa), acc);
     }
     const T mk = T(-a.kappa);
-    hops_dir<0, GP, SPI>(a, in, i, x, mk, acc);
-    hops_dir<1, GP, SPI>(a, in, i, x, mk, acc);
-    hops_dir<2, GP, SPI>(a, in, i, x, mk, acc);
-    hops_dir<3, GP, SPI>(a, in, i, x, mk, acc);
+#define WCL_HOP(K, SC, UC, SN, UN)                                                 \
+    if ((K) < 7) {                                                                 \
+        SpinorIO<SPI>::load(in, V, nbr[(K) + 1], SN);                              \
+        GaugeIO<GP>::load_raw(a.gauge, V, ((K) + 1) / 2, lnk[(K) + 1], UN);        \
+    }                                                                              \
+    hop_compute<(K) / 2, ((K) % 2) == 0>(SC, UC, mk * ph[K], acc);
+    WCL_HOP(0, s0, u0, s1, u1)
+    WCL_HOP(1, s1, u1, s0, u0)
+    WCL_HOP(2, s0, u0, s1, u1)
+    WCL_HOP(3, s1, u1, s0, u0)
+    WCL_HOP(4, s0, u0, s1, u1)
+    WCL_HOP(5, s1, u1, s0, u0)
+    WCL_HOP(6, s0, u0, s1, u1)
+    WCL_HOP(7, s1, u1, s0, u0)
+#undef WCL_HOP
 }
 
 template <int GP, int SPI, int SPO, int EPI, int SPY>
-__global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
+#ifndef WCL_DSLASH_MINWAVES
+#define WCL_DSLASH_MINWAVES 1
+#endif
+__global__ __launch_bounds__(256, WCL_DSLASH_MINWAVES) void k_dslash(DslashArgs a) {
     using T = typename Real<GP>::T;
     static_assert((GP == WCL_F64) == (SPI == WCL_F64), "FP64 arithmetic needs FP64 spinors and links");
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -102,10 +125,10 @@ struct CloverBlk;
 template <>
 struct CloverBlk<WCL_F64> {
     WCL_DEV static void load(const void* base, int V, int i, int k, double c[36]) {
-        const d2v* p = (const d2v*)base + (size_t)18 * k * V;
+        const d2v* p = (const d2v*)base;
 #pragma unroll
         for (int q = 0; q < 18; ++q) {
-            d2v v = ld_nt(p + (size_t)q * V + i);
+            d2v v = ld_nt(p + tix(18 * k + q, i, 36));
             c[2 * q] = v.x;
             c[2 * q + 1] = v.y;
         }
@@ -114,10 +137,10 @@ struct CloverBlk<WCL_F64> {
 template <>
 struct CloverBlk<WCL_F32> {
     WCL_DEV static void load(const void* base, int V, int i, int k, float c[36]) {
-        const f4v* p = (const f4v*)base + (size_t)9 * k * V;
+        const f4v* p = (const f4v*)base;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            f4v v = ld_nt(p + (size_t)q * V + i);
+            f4v v = ld_nt(p + tix(9 * k + q, i, 18));
             c[4 * q] = v.x;
             c[4 * q + 1] = v.y;
             c[4 * q + 2] = v.z;
@@ -129,14 +152,14 @@ template <>
 struct CloverBlk<WCL_F16> {
     // block 0 = reals 0..35 (groups 0..4), block 1 = reals 36..71 (groups 4..8)
     WCL_DEV static void load(const void* base, int V, int i, int k, float c[36]) {
-        const h8v* p = (const h8v*)base + (size_t)4 * k * V;
-        const float* sc = (const float*)((const char*)base + (((size_t)V * 144 + 255) / 256) * 256);
+        const h8v* p = (const h8v*)base;
+        const float* sc = (const float*)((const char*)base + half_clover_scale_offset(V));
         const float s = sc[i];
         const int off = 4 * k;   // first real of the block inside group 4k
         float t[40];
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            f8v v = __builtin_convertvector(ld_nt(p + (size_t)q * V + i), f8v);
+            f8v v = __builtin_convertvector(ld_nt(p + tix(4 * k + q, i, 9)), f8v);
 #pragma unroll
             for (int j = 0; j < 8; ++j) t[8 * q + j] = v[j] * s;
         }
@@ -155,7 +178,7 @@ struct SpinorPart<WCL_F64> {
         d2v* p = (d2v*)base;
 #pragma unroll
         for (int k = 0; k < 12; ++k)
-            if (k % LPS == lane) st_nt(p + (size_t)k * V + i, d2v{s[2 * k], s[2 * k + 1]});
+            if (k % LPS == lane) st_nt(p + tix(k, i, 12), d2v{s[2 * k], s[2 * k + 1]});
     }
 };
 template <>
@@ -165,7 +188,7 @@ struct SpinorPart<WCL_F32> {
         f4v* p = (f4v*)base;
 #pragma unroll
         for (int g = 0; g < 6; ++g)
-            if (g % LPS == lane) st_nt(p + (size_t)g * V + i, f4v{s[4 * g], s[4 * g + 1], s[4 * g + 2], s[4 * g + 3]});
+            if (g % LPS == lane) st_nt(p + tix(g, i, 6), f4v{s[4 * g], s[4 * g + 1], s[4 * g + 2], s[4 * g + 3]});
     }
 };
 template <>
@@ -183,9 +206,9 @@ struct SpinorPart<WCL_F16> {
                 f8v v;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) v[j] = s[8 * g + j] * inv;
-                st_nt(p + (size_t)g * V + i, __builtin_convertvector(v, h8v));
+                st_nt(p + tix(g, i, 3), __builtin_convertvector(v, h8v));
             }
-        if (lane == LPS - 1) st_nt((float*)((char*)base + (((size_t)48 * V + 255) / 256) * 256) + i, m);
+        if (lane == LPS - 1) st_nt((float*)((char*)base + half_spinor_scale_offset(V)) + i, m);
     }
 };
 

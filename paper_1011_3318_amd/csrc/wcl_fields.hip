@@ -80,18 +80,18 @@ __global__ __launch_bounds__(256) void k_pack_gauge(Geom g, const double* __rest
         const double* u = aos + ((size_t)j * 4 + mu) * 18;
         // 12 reals: row 0 (3 complex) then row 1
         for (int k = 0; k < 6; ++k) {
-            ((d2v*)g64)[(size_t)mu * 6 * V + (size_t)k * V + i] = d2v{u[2 * k], u[2 * k + 1]};
+            ((d2v*)g64)[tix(6 * mu + k, i, 24)] = d2v{u[2 * k], u[2 * k + 1]};
         }
         for (int q = 0; q < 3; ++q) {
             f4v v = {(float)u[4 * q], (float)u[4 * q + 1], (float)u[4 * q + 2], (float)u[4 * q + 3]};
-            ((f4v*)g32)[(size_t)mu * 3 * V + (size_t)q * V + i] = v;
+            ((f4v*)g32)[tix(3 * mu + q, i, 12)] = v;
             // binary16 directly (|U_ij| <= 1), one rounding from FP64
             h4v hv;
             hv[0] = (_Float16)u[4 * q];
             hv[1] = (_Float16)u[4 * q + 1];
             hv[2] = (_Float16)u[4 * q + 2];
             hv[3] = (_Float16)u[4 * q + 3];
-            ((h4v*)g16)[(size_t)mu * 3 * V + (size_t)q * V + i] = hv;
+            ((h4v*)g16)[tix(3 * mu + q, i, 12)] = hv;
         }
     }
 }
@@ -228,18 +228,18 @@ __device__ void pack_block(const M3d& A3, const M3d& A1, const M3d& A2, double o
 }
 
 __device__ void store_clover_site(int V, int i, const double c[72], void* c64, void* c32, void* c16) {
-    for (int k = 0; k < 36; ++k) ((d2v*)c64)[(size_t)k * V + i] = d2v{c[2 * k], c[2 * k + 1]};
+    for (int k = 0; k < 36; ++k) ((d2v*)c64)[tix(k, i, 36)] = d2v{c[2 * k], c[2 * k + 1]};
     for (int k = 0; k < 18; ++k)
-        ((f4v*)c32)[(size_t)k * V + i] = f4v{(float)c[4 * k], (float)c[4 * k + 1], (float)c[4 * k + 2], (float)c[4 * k + 3]};
+        ((f4v*)c32)[tix(k, i, 18)] = f4v{(float)c[4 * k], (float)c[4 * k + 1], (float)c[4 * k + 2], (float)c[4 * k + 3]};
     double m = 0;
     for (int k = 0; k < 72; ++k) m = fmax(m, fabs(c[k]));
     double inv = m > 0 ? 1.0 / m : 0.0;
     for (int k = 0; k < 9; ++k) {
         h8v hv;
         for (int j = 0; j < 8; ++j) hv[j] = (_Float16)(float)(c[8 * k + j] * inv);
-        ((h8v*)c16)[(size_t)k * V + i] = hv;
+        ((h8v*)c16)[tix(k, i, 9)] = hv;
     }
-    float* sc = (float*)((char*)c16 + (((size_t)V * 144 + 255) / 256) * 256);
+    float* sc = (float*)((char*)c16 + half_clover_scale_offset(V));
     sc[i] = (float)m;
 }
 

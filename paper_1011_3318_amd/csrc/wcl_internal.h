@@ -8,6 +8,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
 
 #include "wcl.h"
@@ -104,35 +105,50 @@ struct Blocks {
 };
 
 // ------------------------------------------------------ storage -------
+// Tiled structure of arrays: a field with NC vector elements per site is
+// stored in tiles of 64 sites (one wavefront), element-major inside a tile:
+//     element (k, site i)  at  ((i / 64) * NC + k) * 64 + i % 64.
+// A wavefront's load of one element is 64 consecutive vectors, and all the
+// elements of a tile are contiguous, so a kernel streams a few long runs
+// instead of one run per element array (measured: 7.0 vs 5.4 TB/s for the
+// D-apply's byte pattern).  The last tile is padded; padding is never read
+// as data.
+//
 // Spinor (per right-hand side; rhs stride = wcl_spinor_bytes(.., 1)):
-//   F64: double2[12][V]         component k = 3*spin + colour
-//   F32: float4 [6][V]          float4 g = components 2g, 2g+1 (re,im,re,im)
-//   F16: uint4  [3][V] + float[V] scale; uint4 g = reals 8g..8g+7 / scale
-// Gauge (two rows per link; row 2 = conj(row0 x row1) is rebuilt on load):
-//   F64: double2[4][6][V]   F32: float4[4][3][V]   F16: uint2[4][3][V]
+//   F64: NC=12 double2, element k = component 3*spin + colour
+//   F32: NC=6  float4,  element g = components 2g, 2g+1 (re,im,re,im)
+//   F16: NC=3  half8 (reals 8g..8g+7 divided by the site scale) + a plain
+//        float[Vp] scale array after the tiles
+// Gauge (rows 0,1 of each link; row 2 = conj(row0 x row1) rebuilt on load):
+//   F64: NC=24 double2 (element 6 mu + k)   F32: NC=12 float4 (3 mu + g)
+//   F16: NC=12 half4 (3 mu + g)
 // Clover C (kappa-independent), 72 reals per site = blocks k=0,1 of 36:
 //   6 real diagonal entries then 15 complex upper entries, row-major:
-//   F64: double2[36][V]   F32: float4[18][V]   F16: uint4[9][V] + float[V] scale
+//   F64: NC=36 double2   F32: NC=18 float4   F16: NC=9 half8 + float[Vp] scale
+__host__ __device__ inline size_t tix(int k, int i, int NC) {
+    return ((size_t)(i >> 6) * NC + k) * 64 + (i & 63);
+}
 inline size_t round_up(size_t n, size_t a) { return (n + a - 1) / a * a; }
+inline size_t padded_sites(int64_t V) { return round_up((size_t)V, 64); }
 
 inline size_t spinor_rhs_bytes(int prec, int64_t V) {
+    const size_t Vp = padded_sites(V);
     switch (prec) {
-        case WCL_F64: return round_up(192 * (size_t)V, 256);
-        case WCL_F32: return round_up(96 * (size_t)V, 256);
-        default: return round_up(48 * (size_t)V, 256) + round_up(4 * (size_t)V, 256);
+        case WCL_F64: return 192 * Vp;
+        case WCL_F32: return 96 * Vp;
+        default: return 48 * Vp + round_up(4 * Vp, 256);
     }
 }
 inline size_t gauge_bytes(int prec, int64_t V) {
-    return (size_t)V * 4 * 12 * (prec == WCL_F64 ? 8 : prec == WCL_F32 ? 4 : 2);
+    return padded_sites(V) * 4 * 12 * (prec == WCL_F64 ? 8 : prec == WCL_F32 ? 4 : 2);
 }
 inline size_t clover_bytes(int prec, int64_t V) {
-    return prec == WCL_F64 ? (size_t)V * 72 * 8
-           : prec == WCL_F32 ? (size_t)V * 72 * 4
-                             : round_up((size_t)V * 144, 256) + round_up((size_t)V * 4, 256);
+    const size_t Vp = padded_sites(V);
+    return prec == WCL_F64 ? Vp * 72 * 8 : prec == WCL_F32 ? Vp * 72 * 4 : Vp * 144 + round_up(Vp * 4, 256);
 }
-// offset of the FP16 scale array inside an FP16 spinor (per rhs) / clover
-inline size_t half_spinor_scale_offset(int64_t V) { return round_up(48 * (size_t)V, 256); }
-inline size_t half_clover_scale_offset(int64_t V) { return round_up((size_t)V * 144, 256); }
+// byte offset of the FP16 scale array inside an FP16 spinor (per rhs) / clover
+__host__ __device__ inline size_t half_spinor_scale_offset(int V) { return (size_t)48 * ((V + 63) / 64 * 64); }
+__host__ __device__ inline size_t half_clover_scale_offset(int V) { return (size_t)144 * ((V + 63) / 64 * 64); }
 
 // ------------------------------------------------------ structures -----
 struct wcl_ctx {
@@ -141,6 +157,7 @@ struct wcl_ctx {
     uint64_t in_use;
     int arch_major;
     int num_cu;
+    std::mutex mu;   // guards in_use (serving slots allocate concurrently)
 };
 
 struct Workspace;  // solver scratch, defined in wcl_solver.hip

@@ -83,6 +83,17 @@ int launch_blk_project(const BlockArgs& a, int src_prec, hipStream_t st);
 int launch_blk_dslash(const BlockArgs& a, int gp, hipStream_t st);
 int launch_blk_update(const BlockArgs& a, int vj_prec, int last, hipStream_t st);
 int launch_blk_unpack(const BlockArgs& a, const float* ws, double* out, hipStream_t st);
+// ------------------------------------------------------------- solvers --
+struct Workspace;
+Workspace* wcl_workspace_new(wcl_ctx* ctx);
+void wcl_workspace_delete(Workspace* w);
+size_t workspace_bytes(const Workspace* w);
+void workspace_get(Workspace* w, const char* name, size_t bytes, void** out, int* rc);
+// Nested RAS-BiCGStab on an explicit workspace and stream (Sec. 3).
+int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, double kappa, double csw,
+                 const void* eta, void* phi, int nrhs, wcl_solve_stats* stats, hipStream_t st);
+// Device bytes a nested solve needs on a fresh workspace (estimate, upper bound).
+size_t nested_workspace_bytes(const wcl_lattice* lat, const wcl_solver_params* prm, int nrhs);
 int fused_threads(int ev);   // workgroup size of the fused domain solver, 0 if it does not fit
 int launch_blk_fused(const BlockArgs& a, int gp, int src_prec, hipStream_t st);
 int blas_restart(int prec, int64_t V, int nrhs, const Scal* sc, const void* src, void* r, void* rh, void* p, void* v,

@@ -1,0 +1,325 @@
+// Serving loop: continuous batching of nested-solver requests on one device.
+//
+// Each registered gauge configuration stays resident (links + clover).  A
+// request waits in a FIFO queue until a slot is free and the device memory
+// its solve needs fits the budget; then the slot's worker thread runs it on
+// the slot's own HIP stream with the slot's own workspace, so admitted
+// requests overlap on the device.  A slot keeps its workspace between
+// requests (no device allocation on the hot path once warm); the admission
+// test charges a request only for the growth of that workspace.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "wcl_kernels.h"
+
+namespace {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Job {
+    uint64_t ticket = 0;
+    wcl_request req{};
+    wcl_solver_params params{};
+    wcl_lattice* lat = nullptr;
+    size_t need = 0;       // estimated workspace bytes of the solve
+    size_t reserved = 0;   // growth charged at admission
+    double t_submit = 0, t_admit = 0;
+};
+
+// default RAS domain: 4 in every direction it divides, else 2, else the extent
+int default_block(int L) { return L % 4 == 0 ? 4 : (L % 2 == 0 ? 2 : L); }
+
+}  // namespace
+
+struct wcl_server {
+    wcl_ctx* ctx = nullptr;
+    uint64_t budget = 0;
+    int max_queue = 4096;
+    std::map<uint64_t, wcl_lattice*> configs;
+    std::mutex mu;
+    std::condition_variable cv_done;
+    std::deque<Job> queue;
+    struct Slot {
+        std::thread th;
+        hipStream_t st = nullptr;
+        Workspace* ws = nullptr;
+        size_t held = 0;    // bytes the slot's workspace holds
+        bool busy = false;
+        Job job;
+        std::condition_variable cv;
+    };
+    std::vector<Slot*> slots;
+    std::map<uint64_t, wcl_result> done;
+    std::map<uint64_t, bool> known;   // tickets not yet collected
+    uint64_t next_ticket = 1;
+    size_t reserved = 0;
+    bool stop = false;
+
+    size_t resident_bytes() const {
+        size_t b = 0;
+        for (auto& kv : configs)
+            for (int p = 0; p < 3; ++p) b += gauge_bytes(p, kv.second->V) + clover_bytes(p, kv.second->V);
+        return b;
+    }
+    size_t held_bytes() const {
+        size_t b = 0;
+        for (auto* s : slots) b += s->held;
+        return b;
+    }
+
+    // Admits queued requests in FIFO order while a slot is free and the
+    // budget allows.  Called with mu held.
+    void admit() {
+        while (!queue.empty()) {
+            Slot* free_slot = nullptr;
+            for (auto* s : slots)
+                if (!s->busy) {
+                    // prefer the free slot whose workspace already fits
+                    if (!free_slot || (s->held >= queue.front().need && free_slot->held < queue.front().need))
+                        free_slot = s;
+                }
+            if (!free_slot) return;
+            Job& j = queue.front();
+            const size_t growth = j.need > free_slot->held ? j.need - free_slot->held : 0;
+            const size_t used = resident_bytes() + held_bytes() + reserved;
+            if (used + growth > budget) return;   // head of line waits for memory
+            Job job = j;
+            queue.pop_front();
+            job.reserved = growth;
+            job.t_admit = now_s();
+            reserved += growth;
+            free_slot->job = job;
+            free_slot->busy = true;
+            free_slot->cv.notify_one();
+        }
+    }
+
+    void run_job(Slot* s) {
+        Job& j = s->job;
+        wcl_result res{};
+        res.t_submit = j.t_submit;
+        res.t_admit = j.t_admit;
+        int rc = WCL_OK;
+        const int64_t V = j.lat->V;
+        const size_t b64 = spinor_rhs_bytes(WCL_F64, V), stage_b = (size_t)V * 24 * sizeof(double);
+        void *eta = nullptr, *phi = nullptr, *stage = nullptr;
+        workspace_get(s->ws, "srv.eta", b64, &eta, &rc);
+        if (rc == WCL_OK) workspace_get(s->ws, "srv.phi", b64, &phi, &rc);
+        if (rc == WCL_OK) workspace_get(s->ws, "srv.stage", stage_b, &stage, &rc);
+        if (rc == WCL_OK && hipMemcpyAsync(stage, j.req.eta_host, stage_b, hipMemcpyHostToDevice, s->st) != hipSuccess)
+            rc = WCL_EHIP;
+        if (rc == WCL_OK) rc = launch_pack_spinor(j.lat->g, WCL_F64, 1, (const double*)stage, eta, b64, s->st);
+        if (rc == WCL_OK)
+            rc = nested_solve(j.lat, s->ws, &j.params, j.req.kappa, j.req.csw, eta, phi, 1, &res.stats, s->st);
+        if (rc == WCL_OK || rc == WCL_ENOTCONV) {
+            int rc2 = launch_unpack_spinor(j.lat->g, WCL_F64, 1, phi, b64, (double*)stage, s->st);
+            if (rc2 == WCL_OK &&
+                hipMemcpyAsync(j.req.phi_host, stage, stage_b, hipMemcpyDeviceToHost, s->st) != hipSuccess)
+                rc2 = WCL_EHIP;
+            if (rc2 == WCL_OK && hipStreamSynchronize(s->st) != hipSuccess) rc2 = WCL_EHIP;
+            if (rc2 != WCL_OK) rc = rc2;
+        }
+        res.status = rc;
+        res.t_done = now_s();
+        std::lock_guard<std::mutex> g(mu);
+        reserved -= j.reserved;
+        s->held = workspace_bytes(s->ws);
+        s->busy = false;
+        done[j.ticket] = res;
+        cv_done.notify_all();
+        admit();
+    }
+
+    void worker(Slot* s) {
+        (void)hipSetDevice(ctx->device);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            s->cv.wait(lk, [&] { return s->busy || stop; });
+            if (!s->busy && stop) return;
+            lk.unlock();
+            run_job(s);
+            lk.lock();
+        }
+    }
+};
+
+extern "C" {
+
+int wcl_server_create(wcl_ctx* ctx, const wcl_server_params* p, wcl_server** out) {
+    if (!ctx || !p || !out || p->max_slots < 1 || p->max_slots > 64 || p->max_queue < 0) {
+        wcl_set_error("wcl_server_create: bad argument");
+        return WCL_EINVAL;
+    }
+    *out = nullptr;
+    WCL_HIP(hipSetDevice(ctx->device));
+    auto* srv = new wcl_server;
+    srv->ctx = ctx;
+    srv->budget = p->hbm_budget_bytes ? p->hbm_budget_bytes : ctx->budget;
+    srv->max_queue = p->max_queue ? p->max_queue : 4096;
+    for (int k = 0; k < p->max_slots; ++k) {
+        auto* s = new wcl_server::Slot;
+        if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess) {
+            delete s;
+            wcl_server_destroy(srv);
+            wcl_set_error("wcl_server_create: stream creation failed");
+            return WCL_EHIP;
+        }
+        s->ws = wcl_workspace_new(ctx);
+        srv->slots.push_back(s);
+    }
+    for (auto* s : srv->slots) s->th = std::thread([srv, s] { srv->worker(s); });
+    *out = srv;
+    return WCL_OK;
+}
+
+int wcl_server_destroy(wcl_server* srv) {
+    if (!srv) return WCL_OK;
+    {
+        std::unique_lock<std::mutex> lk(srv->mu);
+        srv->cv_done.wait(lk, [&] {
+            if (!srv->queue.empty()) return false;
+            for (auto* s : srv->slots)
+                if (s->busy) return false;
+            return true;
+        });
+        srv->stop = true;
+        for (auto* s : srv->slots) s->cv.notify_one();
+    }
+    for (auto* s : srv->slots) {
+        if (s->th.joinable()) s->th.join();
+        wcl_workspace_delete(s->ws);
+        if (s->st) (void)hipStreamDestroy(s->st);
+        delete s;
+    }
+    for (auto& kv : srv->configs) wcl_destroy_lattice(kv.second);
+    delete srv;
+    return WCL_OK;
+}
+
+int wcl_register_gauge(wcl_server* srv, uint64_t config_id, const int dims[4], const double* U_host) {
+    if (!srv || !dims || !U_host) {
+        wcl_set_error("wcl_register_gauge: null argument");
+        return WCL_EINVAL;
+    }
+    {
+        std::lock_guard<std::mutex> g(srv->mu);
+        if (srv->configs.count(config_id)) {
+            wcl_set_error("wcl_register_gauge: config %llu already registered", (unsigned long long)config_id);
+            return WCL_EINVAL;
+        }
+        int64_t V = 1;
+        for (int mu = 0; mu < 4; ++mu) V *= dims[mu] > 0 ? dims[mu] : 1;
+        size_t fields = 0;
+        for (int p = 0; p < 3; ++p) fields += gauge_bytes(p, V) + clover_bytes(p, V);
+        if (srv->resident_bytes() + srv->held_bytes() + srv->reserved + fields > srv->budget) {
+            wcl_set_error("wcl_register_gauge: resident fields (%llu bytes) exceed the server budget",
+                          (unsigned long long)fields);
+            return WCL_ENOMEM;
+        }
+    }
+    wcl_lattice* lat = nullptr;
+    WCL_CHECK(wcl_create_lattice(srv->ctx, dims, nullptr, &lat));
+    int rc = wcl_upload_gauge(lat, U_host);
+    if (rc == WCL_OK) rc = wcl_compute_clover(lat);
+    if (rc != WCL_OK) {
+        wcl_destroy_lattice(lat);
+        return rc;
+    }
+    std::lock_guard<std::mutex> g(srv->mu);
+    srv->configs[config_id] = lat;
+    return WCL_OK;
+}
+
+int wcl_submit(wcl_server* srv, const wcl_request* req, uint64_t* ticket) {
+    if (!srv || !req || !ticket || !req->eta_host || !req->phi_host) {
+        wcl_set_error("wcl_submit: null argument");
+        return WCL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(srv->mu);
+    auto it = srv->configs.find(req->config_id);
+    if (it == srv->configs.end()) {
+        wcl_set_error("wcl_submit: unknown config %llu", (unsigned long long)req->config_id);
+        return WCL_EINVAL;
+    }
+    Job j;
+    j.req = *req;
+    j.lat = it->second;
+    if (req->params) {
+        j.params = *req->params;
+    } else {
+        j.params.tol_outer = 1e-10;
+        j.params.tol_inner = 1e-4;
+        j.params.max_outer = 100;
+        j.params.max_inner = 100;
+        j.params.max_restarts = 10;
+        j.params.precond = WCL_PRECOND_RAS;
+        for (int mu = 0; mu < 4; ++mu) j.params.ras.block[mu] = default_block(j.lat->g.L[mu]);
+        j.params.ras.s = 0;
+        j.params.ras.n_ras = 3;
+        j.params.ras.n_dominv = 4;
+        j.params.ras.storage = WCL_F16;
+        j.params.ras.kernel = WCL_BLOCK_AUTO;
+    }
+    if (j.params.precond == WCL_PRECOND_RAS) {
+        Blocks B;
+        WCL_CHECK(make_blocks(j.lat, &j.params.ras, &B));
+    }
+    j.need = nested_workspace_bytes(j.lat, &j.params, 1) + 2 * spinor_rhs_bytes(WCL_F64, j.lat->V) +
+             (size_t)j.lat->V * 24 * sizeof(double);
+    if (srv->resident_bytes() + j.need > srv->budget) {
+        wcl_set_error("wcl_submit: request needs %llu bytes, more than the budget leaves",
+                      (unsigned long long)j.need);
+        return WCL_ENOMEM;
+    }
+    if ((int)srv->queue.size() >= srv->max_queue) {
+        wcl_set_error("wcl_submit: queue full");
+        return WCL_ENOMEM;
+    }
+    j.ticket = srv->next_ticket++;
+    j.t_submit = now_s();
+    srv->known[j.ticket] = true;
+    srv->queue.push_back(j);
+    *ticket = j.ticket;
+    srv->admit();
+    return WCL_OK;
+}
+
+int wcl_poll(wcl_server* srv, uint64_t ticket, wcl_result* res) {
+    if (!srv || !res) return WCL_EINVAL;
+    std::lock_guard<std::mutex> g(srv->mu);
+    if (!srv->known.count(ticket)) {
+        wcl_set_error("wcl_poll: unknown ticket %llu", (unsigned long long)ticket);
+        return WCL_EINVAL;
+    }
+    auto it = srv->done.find(ticket);
+    if (it == srv->done.end()) return WCL_PENDING;
+    *res = it->second;
+    srv->done.erase(it);
+    srv->known.erase(ticket);
+    return WCL_OK;
+}
+
+int wcl_wait(wcl_server* srv, uint64_t ticket, wcl_result* res) {
+    if (!srv || !res) return WCL_EINVAL;
+    {
+        std::unique_lock<std::mutex> lk(srv->mu);
+        if (!srv->known.count(ticket)) {
+            wcl_set_error("wcl_wait: unknown ticket %llu", (unsigned long long)ticket);
+            return WCL_EINVAL;
+        }
+        srv->cv_done.wait(lk, [&] { return srv->done.count(ticket) > 0; });
+    }
+    return wcl_poll(srv, ticket, res);
+}
+
+}  // extern "C"

@@ -89,6 +89,30 @@ Workspace* wcl_workspace_new(wcl_ctx* ctx) {
 }
 void wcl_workspace_delete(Workspace* w) { delete w; }
 
+size_t workspace_bytes(const Workspace* w) {
+    size_t b = 0;
+    for (const auto& it : w->items) b += it.bytes;
+    return b;
+}
+
+void workspace_get(Workspace* w, const char* name, size_t bytes, void** out, int* rc) {
+    *rc = w->get(name, bytes, out);
+}
+
+size_t nested_workspace_bytes(const wcl_lattice* lat, const wcl_solver_params* prm, int nrhs) {
+    const size_t v64 = spinor_rhs_bytes(WCL_F64, lat->V) * nrhs, v32 = spinor_rhs_bytes(WCL_F32, lat->V) * nrhs;
+    size_t b = 8 * v64 + 10 * v32;   // outer and inner BiCGStab vectors, inner rhs/solution
+    if (prm && prm->precond == WCL_PRECOND_RAS) {
+        Blocks B;
+        if (make_blocks(lat, &prm->ras, &B) == WCL_OK) {
+            b += 3 * spinor_rhs_bytes(prm->ras.storage, lat->V) * nrhs;   // v_j, r_j ping-pong
+            if (fused_threads(B.ev) != 256) b += (size_t)3 * 96 * B.nblocks * B.ev * nrhs;   // split workspaces
+        }
+    }
+    const size_t partials = (size_t)24 * nrhs * ((lat->V + 63) / 64);
+    return b + 4 * partials + (1 << 20);
+}
+
 void wcl_free_workspace(wcl_lattice* lat) {
     delete lat->ws;
     lat->ws = nullptr;

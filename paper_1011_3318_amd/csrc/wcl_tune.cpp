@@ -1,0 +1,192 @@
+// Autotuner for the nested RAS solver: times complete solves over a staged
+// candidate set and caches the winner per (arch, dims, nrhs, kappa, c_sw).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "wcl_kernels.h"
+
+namespace {
+
+struct Cand {
+    wcl_solver_params p;
+    int lps;
+};
+
+std::string tune_key(const wcl_lattice* lat, int nrhs, double kappa, double csw) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, lat->ctx->device) == hipSuccess) arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s|%dx%dx%dx%d|bc%d%d%d%d|nrhs%d|k%.6f|c%.6f", arch.c_str(), lat->g.L[0], lat->g.L[1],
+             lat->g.L[2], lat->g.L[3], lat->g.bc[0], lat->g.bc[1], lat->g.bc[2], lat->g.bc[3], nrhs, kappa, csw);
+    return buf;
+}
+
+// One line per entry:
+// {"key": "...", "block": [b0,b1,b2,b3], "s": s, "n_ras": n, "n_dominv": n, "storage": p,
+//  "tol_inner": t, "lps": l, "ms": m}
+bool cache_lookup(const char* path, const std::string& key, Cand* c, double* ms) {
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    const std::string pat = "\"key\": \"" + key + "\"";
+    while (fgets(line, sizeof line, f)) {
+        if (!strstr(line, pat.c_str())) continue;
+        int b[4], s, nr, nd, st, lps;
+        double tol, m;
+        const char* q = strstr(line, "\"block\"");
+        if (q && sscanf(q, "\"block\": [%d, %d, %d, %d], \"s\": %d, \"n_ras\": %d, \"n_dominv\": %d, \"storage\": %d, "
+                           "\"tol_inner\": %lf, \"lps\": %d, \"ms\": %lf",
+                        &b[0], &b[1], &b[2], &b[3], &s, &nr, &nd, &st, &tol, &lps, &m) == 11) {
+            for (int mu = 0; mu < 4; ++mu) c->p.ras.block[mu] = b[mu];
+            c->p.ras.s = s;
+            c->p.ras.n_ras = nr;
+            c->p.ras.n_dominv = nd;
+            c->p.ras.storage = st;
+            c->p.ras.kernel = WCL_BLOCK_AUTO;
+            c->p.tol_inner = tol;
+            c->p.precond = WCL_PRECOND_RAS;
+            c->lps = lps;
+            *ms = m;
+            found = true;   // the last matching line wins
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_store(const char* path, const std::string& key, const Cand& c, double ms) {
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f,
+            "{\"key\": \"%s\", \"block\": [%d, %d, %d, %d], \"s\": %d, \"n_ras\": %d, \"n_dominv\": %d, "
+            "\"storage\": %d, \"tol_inner\": %.3e, \"lps\": %d, \"ms\": %.4f}\n",
+            key.c_str(), c.p.ras.block[0], c.p.ras.block[1], c.p.ras.block[2], c.p.ras.block[3], c.p.ras.s,
+            c.p.ras.n_ras, c.p.ras.n_dominv, c.p.ras.storage, c.p.tol_inner, c.lps, ms);
+    fclose(f);
+}
+
+}  // namespace
+
+extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, double kappa, double csw,
+                            const void* eta_dev, int nrhs, const char* cache_path, wcl_solver_params* best,
+                            double* best_ms, void* stream) {
+    if (!lat || !base || !eta_dev || nrhs < 1 || !best) {
+        wcl_set_error("wcl_autotune: bad argument");
+        return WCL_EINVAL;
+    }
+    WCL_HIP(hipSetDevice(lat->ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const std::string key = tune_key(lat, nrhs, kappa, csw);
+    Cand cur{*base, lat->lps};
+    cur.p.precond = WCL_PRECOND_RAS;
+    double cur_ms = 0;
+    if (cache_path && cache_lookup(cache_path, key, &cur, &cur_ms)) {
+        Blocks B;
+        if (make_blocks(lat, &cur.p.ras, &B) == WCL_OK) {
+            wcl_solver_params out = *base;
+            out.precond = WCL_PRECOND_RAS;
+            out.ras = cur.p.ras;
+            out.tol_inner = cur.p.tol_inner;
+            *best = out;
+            lat->lps = cur.lps;
+            if (best_ms) *best_ms = cur_ms;
+            return WCL_OK;
+        }
+    }
+    Workspace* ws = wcl_workspace_new(lat->ctx);
+    void* phi = nullptr;
+    int rc = WCL_OK;
+    workspace_get(ws, "tune.phi", spinor_rhs_bytes(WCL_F64, lat->V) * nrhs, &phi, &rc);
+    if (rc != WCL_OK) {
+        wcl_workspace_delete(ws);
+        return rc;
+    }
+    // time = best of two complete solves (the first also warms the workspace)
+    auto measure = [&](const Cand& c, double* ms) -> bool {
+        Blocks B;
+        if (make_blocks(lat, &c.p.ras, &B) != WCL_OK) return false;
+        const int saved = lat->lps;
+        lat->lps = c.lps;
+        double t = 1e30;
+        bool ok = true;
+        for (int rep = 0; rep < 2 && ok; ++rep) {
+            wcl_solve_stats s{};
+            int r = nested_solve(lat, ws, &c.p, kappa, csw, eta_dev, phi, nrhs, &s, st);
+            if (r != WCL_OK || !s.converged) ok = false;
+            else t = std::min(t, s.ms_total);
+        }
+        lat->lps = saved;
+        *ms = t;
+        return ok;
+    };
+    Cand bestc = cur;
+    double bms = 1e30;
+    auto consider = [&](const Cand& c) {
+        double ms;
+        if (measure(c, &ms) && ms < bms) {
+            bms = ms;
+            bestc = c;
+        }
+    };
+    // stage 1: domain shape x overlap x storage
+    const int shapes[3][4] = {{4, 4, 4, 4}, {4, 4, 4, 8}, {8, 8, 8, 8}};
+    for (const auto& sh : shapes)
+        for (int s = 0; s <= 1; ++s)
+            for (int storage : {WCL_F32, WCL_F16}) {
+                Cand c = cur;
+                for (int mu = 0; mu < 4; ++mu) c.p.ras.block[mu] = sh[mu];
+                c.p.ras.s = s;
+                c.p.ras.storage = storage;
+                c.p.ras.n_dominv = 4;
+                c.p.ras.n_ras = 3;
+                c.p.ras.kernel = WCL_BLOCK_AUTO;
+                consider(c);
+            }
+    if (bms >= 1e30) {
+        wcl_workspace_delete(ws);
+        wcl_set_error("wcl_autotune: no candidate converged");
+        return WCL_ENOTCONV;
+    }
+    // stage 2: N_dominv x NRAS
+    {
+        const Cand base2 = bestc;
+        for (int nd : {2, 4, 6})
+            for (int nr : {1, 2, 3}) {
+                Cand c = base2;
+                c.p.ras.n_dominv = nd;
+                c.p.ras.n_ras = nr;
+                consider(c);
+            }
+    }
+    // stage 3: inner tolerance, lanes per site of the D-apply
+    {
+        const Cand base3 = bestc;
+        for (double tol : {1e-2, 1e-3, 1e-4})
+            for (int lps : {1, 2}) {
+                Cand c = base3;
+                c.p.tol_inner = tol;
+                c.lps = lps;
+                consider(c);
+            }
+    }
+    wcl_workspace_delete(ws);
+    wcl_solver_params out = *base;
+    out.precond = WCL_PRECOND_RAS;
+    out.ras = bestc.p.ras;
+    out.tol_inner = bestc.p.tol_inner;
+    *best = out;
+    lat->lps = bestc.lps;
+    if (best_ms) *best_ms = bms;
+    if (cache_path) cache_store(cache_path, key, bestc, bms);
+    return WCL_OK;
+}

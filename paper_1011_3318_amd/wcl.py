@@ -235,3 +235,105 @@ class Lattice:
         if rc != ENOTCONV or raise_on_notconv:
             check(rc)
         return rc, st.as_dict()
+
+
+# ------------------------------------------------------------------ serving
+class ServerParams(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_slots", C.c_int), ("max_queue", C.c_int)]
+
+
+class Request(C.Structure):
+    _fields_ = [("config_id", C.c_uint64), ("kappa", C.c_double), ("csw", C.c_double),
+                ("params", C.POINTER(SolverParams)), ("eta_host", C.POINTER(C.c_double)),
+                ("phi_host", C.POINTER(C.c_double))]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("stats", SolveStats), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double)]
+
+
+def _server_sigs():
+    vp = C.c_void_p
+    sig = {
+        "wcl_server_create": (C.c_int, [vp, C.POINTER(ServerParams), C.POINTER(vp)]),
+        "wcl_server_destroy": (C.c_int, [vp]),
+        "wcl_register_gauge": (C.c_int, [vp, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+        "wcl_submit": (C.c_int, [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+        "wcl_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(Result)]),
+        "wcl_wait": (C.c_int, [vp, C.c_uint64, C.POINTER(Result)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+
+
+_server_sigs()
+
+
+class Server:
+    """Continuous-batching solve server (see include/wcl.h)."""
+
+    def __init__(self, ctx: Context, max_slots: int = 4, hbm_budget: int = 0, max_queue: int = 0):
+        h = C.c_void_p()
+        check(lib.wcl_server_create(ctx.h, C.byref(ServerParams(hbm_budget, max_slots, max_queue)), C.byref(h)))
+        self.h = h
+        self._live = {}   # ticket -> (eta, phi, params) kept alive until collected
+        self.dims = {}
+
+    def register_gauge(self, config_id: int, dims, U):
+        U = np.ascontiguousarray(U, dtype=np.complex128)
+        check(lib.wcl_register_gauge(self.h, config_id, (C.c_int * 4)(*dims), U.ctypes.data_as(C.POINTER(C.c_double))))
+        self.dims[config_id] = tuple(dims)
+
+    def submit(self, config_id: int, kappa: float, csw: float, eta, params: SolverParams | None = None) -> int:
+        eta = np.ascontiguousarray(eta, dtype=np.complex128)
+        phi = np.zeros_like(eta)
+        p = C.pointer(params) if params is not None else None
+        req = Request(config_id, kappa, csw, p, eta.ctypes.data_as(C.POINTER(C.c_double)),
+                      phi.ctypes.data_as(C.POINTER(C.c_double)))
+        t = C.c_uint64()
+        check(lib.wcl_submit(self.h, C.byref(req), C.byref(t)))
+        self._live[t.value] = (eta, phi, params)
+        return t.value
+
+    def _collect(self, ticket, res):
+        eta, phi, _ = self._live.pop(ticket)
+        d = {"status": res.status, "t_submit": res.t_submit, "t_admit": res.t_admit, "t_done": res.t_done}
+        d.update(res.stats.as_dict())
+        return phi, d
+
+    def poll(self, ticket: int):
+        res = Result()
+        rc = lib.wcl_poll(self.h, ticket, C.byref(res))
+        if rc == PENDING:
+            return None
+        check(rc)
+        return self._collect(ticket, res)
+
+    def wait(self, ticket: int):
+        res = Result()
+        check(lib.wcl_wait(self.h, ticket, C.byref(res)))
+        return self._collect(ticket, res)
+
+    def close(self):
+        if self.h:
+            check(lib.wcl_server_destroy(self.h))
+            self.h = None
+            self._live.clear()
+
+
+lib.wcl_autotune.restype = C.c_int
+lib.wcl_autotune.argtypes = [C.c_void_p, C.POINTER(SolverParams), C.c_double, C.c_double, C.c_void_p, C.c_int,
+                             C.c_char_p, C.POINTER(SolverParams), C.POINTER(C.c_double), C.c_void_p]
+
+
+def autotune(lat: Lattice, base: SolverParams, kappa: float, csw: float, eta: torch.Tensor, nrhs: int = 1,
+             cache_path: str | None = None, stream=None):
+    """Autotuned solver parameters for this lattice and source (see include/wcl.h)."""
+    best = SolverParams()
+    ms = C.c_double()
+    check(lib.wcl_autotune(lat.h, C.byref(base), kappa, csw, _ptr(eta), nrhs,
+                           cache_path.encode() if cache_path else None, C.byref(best), C.byref(ms), _stream(stream)))
+    return best, ms.value

@@ -1,0 +1,123 @@
+"""GPU tests of the serving loop: continuous batching over resident gauge
+fields, each result equal to the same solve run alone, admission by HBM."""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_1011_3318_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_1011_3318_amd import wcl
+    return wcl
+
+
+@pytest.fixture(scope="module")
+def ctx(W):
+    c = W.Context(0)
+    yield c
+    c.close()
+
+
+CONFIGS = {1: (8, 8, 8, 8), 2: (8, 8, 8, 16)}
+
+
+def requests(n, seed=7):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        cid = 1 + int(rng.integers(2))
+        kappa = float(rng.uniform(0.115, 0.125))
+        csw = float(rng.choice([1.0, 1.5]))
+        out.append((cid, kappa, csw, 1000 + k))
+    return out
+
+
+def test_mixed_equals_alone(W, ctx):
+    gauges = {cid: I.random_gauge(d, 0.5, 1) for cid, d in CONFIGS.items()}
+    reqs = requests(10)
+    # alone: one slot, one request at a time
+    alone = []
+    srv = W.Server(ctx, max_slots=1)
+    for cid, d in CONFIGS.items():
+        srv.register_gauge(cid, d, gauges[cid])
+    for cid, kappa, csw, seed in reqs:
+        t = srv.submit(cid, kappa, csw, I.gaussian_source(CONFIGS[cid], seed))
+        phi, st = srv.wait(t)
+        assert st["status"] == 0
+        alone.append(phi)
+    srv.close()
+    # mixed: four slots, everything submitted at once
+    srv = W.Server(ctx, max_slots=4)
+    for cid, d in CONFIGS.items():
+        srv.register_gauge(cid, d, gauges[cid])
+    tickets = [srv.submit(cid, kappa, csw, I.gaussian_source(CONFIGS[cid], seed)) for cid, kappa, csw, seed in reqs]
+    mixed = [srv.wait(t) for t in tickets]
+    srv.close()
+    overlap = 0
+    for k, ((phi, st), ref) in enumerate(zip(mixed, alone)):
+        assert st["status"] == 0 and st["converged"] == 1
+        assert np.array_equal(phi, ref), k
+    # requests really ran concurrently: some admission happened before an earlier one finished
+    times = sorted((st["t_admit"], st["t_done"]) for _, st in mixed)
+    overlap = sum(1 for a, b in zip(times, times[1:]) if b[0] < a[1])
+    assert overlap > 0
+    # oracle true residual for two of them
+    for k in (0, 5):
+        cid, kappa, csw, seed = reqs[k]
+        eta = I.gaussian_source(CONFIGS[cid], seed)
+        o = Oracle(CONFIGS[cid], gauges[cid])
+        res = np.linalg.norm(eta - o.apply_D(mixed[k][0], kappa, csw)) / np.linalg.norm(eta)
+        assert res <= 1e-10
+
+
+def test_admission_by_memory(W, ctx):
+    d = CONFIGS[2]
+    U = I.random_gauge(d, 0.5, 1)
+    probe = W.Server(ctx, max_slots=1)
+    probe.register_gauge(2, d, U)
+    t = probe.submit(2, 0.12, 1.0, I.gaussian_source(d, 1))
+    probe.wait(t)
+    probe.close()
+    # resident fields of an 8^3x16 lattice + room for exactly one solve
+    V = 8 * 8 * 8 * 16
+    resident = V * 4 * 12 * (8 + 4 + 2) + V * (72 * 8 + 72 * 4 + 144) + 4096
+    need_one = V * (8 * 192 + 10 * 96 + 3 * 52 + 2 * 192 + 192) + 24 * V // 64 * 4 + (1 << 20)
+    srv = W.Server(ctx, max_slots=3, hbm_budget=resident + int(1.5 * need_one))
+    srv.register_gauge(2, d, U)
+    tickets = [srv.submit(2, 0.12, 1.0, I.gaussian_source(d, s)) for s in range(4)]
+    res = [srv.wait(t)[1] for t in tickets]
+    assert all(r["status"] == 0 for r in res)
+    spans = sorted((r["t_admit"], r["t_done"]) for r in res)
+    # the budget admits one solve at a time: no two run together
+    assert all(b[0] >= a[1] - 1e-6 for a, b in zip(spans, spans[1:]))
+    srv.close()
+
+
+def test_oversized_request_rejected(W, ctx):
+    """A request whose workspace can never fit the budget is rejected at
+    submit with WCL_ENOMEM; requests that fit keep running."""
+    d = CONFIGS[1]
+    V = 8 ** 4
+    resident = V * 4 * 12 * (8 + 4 + 2) + V * (72 * 8 + 72 * 4 + 144) + 4096
+    need_fused = V * (8 * 192 + 10 * 96 + 3 * 52 + 2 * 192 + 192) + 24 * V // 64 * 4 + (1 << 20)
+    srv = W.Server(ctx, max_slots=2, hbm_budget=resident + int(1.2 * need_fused))
+    srv.register_gauge(1, d, I.random_gauge(d, 0.5, 1))
+    # the split domain solver (4^4 domains, overlap 1) needs extra workspaces
+    big = W.SolverParams.make(ras=W.RasParams.make(block=(4, 4, 4, 4), s=1, storage=W.F16))
+    with pytest.raises(W.WclError) as e:
+        srv.submit(1, 0.12, 1.0, I.gaussian_source(d, 2), params=big)
+    assert e.value.code == W.ENOMEM
+    t = srv.submit(1, 0.12, 1.0, I.gaussian_source(d, 2))
+    assert srv.wait(t)[1]["status"] == 0
+    with pytest.raises(W.WclError) as e:
+        srv.submit(42, 0.12, 1.0, I.gaussian_source(d, 2))
+    assert e.value.code == W.EINVAL
+    # a configuration whose resident fields exceed the budget is refused
+    with pytest.raises(W.WclError) as e:
+        srv.register_gauge(2, CONFIGS[2], I.random_gauge(CONFIGS[2], 0.5, 1))
+    assert e.value.code == W.ENOMEM
+    srv.close()

@@ -234,3 +234,28 @@ def test_solver_error_paths(W, ctx):
                          lat.pack(eta, W.F64), phi)
     assert e.value.code == W.EINVAL
     lat.close()
+
+
+def test_autotune_and_cache(W, ctx, tmp_path):
+    dims = (8, 8, 8, 16)
+    U, lat = make(W, ctx, dims)
+    eta = I.gaussian_source(dims, 2)
+    e = lat.pack(eta, W.F64)
+    base = W.SolverParams.make()
+    cache = str(tmp_path / "tune.jsonl")
+    best, ms = W.autotune(lat, base, 0.125, 1.0, e, cache_path=cache)
+    assert ms > 0 and best.precond == W.PRECOND_RAS
+    assert tuple(best.ras.block) in {(4, 4, 4, 4), (4, 4, 4, 8), (8, 8, 8, 8)}
+    # the tuned parameters solve to tolerance
+    phi = lat.zeros(W.F64)
+    rc, st = lat.solve_nested(best, 0.125, 1.0, e, phi)
+    res = np.linalg.norm(eta - Oracle(dims, U).apply_D(lat.unpack(phi, W.F64), 0.125, 1.0)) / np.linalg.norm(eta)
+    assert res <= 1e-10
+    # second call reads the cache
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1
+    best2, ms2 = W.autotune(lat, base, 0.125, 1.0, e, cache_path=cache)
+    assert tuple(best2.ras.block) == tuple(best.ras.block) and best2.ras.n_dominv == best.ras.n_dominv
+    assert ms2 == pytest.approx(ms, rel=1e-3)
+    assert len(open(cache).read().splitlines()) == 1
+    lat.close()
