@@ -1,15 +1,19 @@
 """Benchmark: time-to-solution of the mixed-precision nested RAS-BiCGStab
 solver on one MI355X, beside the plain FP64 BiCGStab on the same GPU, plus
-the Wilson-clover D-apply against the HBM roofline.
+the Wilson-clover D-apply against the HBM roofline, the 12-source batched
+solve, the 32^4 FP16-storage solve and the serving loop.
 
-Workload (one step = one complete solve to |eta - D phi|/|eta| <= 1e-10):
-  16^3 x 32 lattice, random SU(3) links exp(i eps H) with eps = 0.5 (seed 1),
-  kappa = 0.125, c_sw = 1.0, Gaussian source (seed 2); FP64 outer / FP32 inner
-  BiCGStab preconditioned by RAS with 8^4 domains, overlap s (default 0),
-  N_dominv = 4 minimal-residual steps, NRAS = 3 sweeps.
-Inputs are resident in HBM before the timed region.
+One step = one complete solve of D phi = eta to |eta - D phi|/|eta| <= 1e-10 on
+  16^3 x 32, random SU(3) links exp(i eps H), eps = 0.5 (seed 1),
+  kappa = 0.125, c_sw = 1.0, Gaussian source (seed 2);
+  FP64 outer / FP32 inner BiCGStab right-preconditioned by RAS
+  (N_dominv = 4 minimal-residual steps per sweep).  The domain shape, overlap,
+  storage, sweeps and inner tolerance are picked by the library's autotuner
+  before the timed region; the literal 8^4 (s = 0 and s = 1) domain solves are
+  timed beside it.
+Inputs are resident in HBM before every timed region.
 
-Prints one JSON line (see the design doc for every field).
+Prints one JSON line; --mode selects a single section (dapply, copyref, serve).
 """
 from __future__ import annotations
 
@@ -25,10 +29,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-solution @1e-10 residual vs plain FP64 BiCGStab; D-apply GB/s; p99 ms"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per site of one D application (links 12 reals x 4 + clover
-# 72 reals + spinor in + spinor out, each field touched once)
+# algorithmic bytes per site of one D application: links (4 x 12 reals),
+# clover (72 reals), spinor in and out (24 reals each), every field once;
+# the FP16 fields carry one FP32 scale per site (spinor in/out, clover)
 DAPPLY_BYTES = {0: 1344, 1: 672, 2: 348}
+DAPPLY_12RHS_BYTES_F32 = 12 * 192 + 480
 DAPPLY_FLOPS = 1872
+SERVE_SIZES = [(8, 8, 8, 8), (16, 16, 16, 32), (24, 24, 24, 48), (32, 32, 32, 32)]
+SERVE_WEIGHTS = [4, 3, 2, 1]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
@@ -36,16 +48,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--overlap", type=int, default=0, help="RAS overlap s (depth d = 2s)")
-    ap.add_argument("--block", default="8x8x8x8", help="RAS domain shape, e.g. 8x8x8x8 or 4x4x4x4")
-    ap.add_argument("--storage", default="f32", choices=["f32", "f16"], help="RAS storage precision")
-    ap.add_argument("--n-dominv", type=int, default=4)
-    ap.add_argument("--n-ras", type=int, default=3)
+    ap.add_argument("--mode", default="full", choices=["full", "dapply", "copyref", "serve"],
+                    help="dapply: only the 32^4 FP32 D-apply loop; copyref: a 1 GiB device copy "
+                         "(the reference kernel for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE); serve: only the "
+                         "serving run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dapply", action="store_true")
-    ap.add_argument("--mode", default="full", choices=["full", "dapply", "copyref"],
-                    help="dapply: only the 32^4 FP32 D-apply loop; copyref: a 1 GiB device copy "
-                         "(the reference kernel for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 12-source, 32^4 and serving sections")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
+    ap.add_argument("--slots", type=int, default=4, help="serving: concurrent solve slots")
     return ap.parse_args()
 
 
@@ -59,7 +71,8 @@ def kernel_source_hash() -> str:
 
 def measured_traffic(prec: int, V: int):
     """HBM bytes per launch from the rocprofv3 FETCH_SIZE/WRITE_SIZE runs,
-    if they were taken on the current kernel source; else None."""
+    scaled by the copy-kernel factor, if they were taken on the current
+    kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "dapply_counters.json")
     try:
         with open(path) as fh:
@@ -72,32 +85,153 @@ def measured_traffic(prec: int, V: int):
     return ent.get("bytes_per_launch")
 
 
-def time_dapply(W, torch, lat, prec, n_warm=10, n_timed=100):
-    import numpy as np
-    from paper_1011_3318_amd import inputs as I
-    psi = I.gaussian_source(lat.dims, 2)
-    xs = [lat.pack(psi, prec) for _ in range(3)]
-    ys = [lat.empty(prec) for _ in range(3)]
-    for k in range(n_warm):
-        lat.apply_D(prec, 0.125, 1.0, xs[k % 3], ys[k % 3])
-    torch.cuda.synchronize()
+def event_time_us(torch, fn, n):
+    """Average duration of fn() over n launches on the current stream (HIP events)."""
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s.record()
-    for k in range(n_timed):
-        lat.apply_D(prec, 0.125, 1.0, xs[k % 3], ys[(k + 1) % 3])
+    for k in range(n):
+        fn(k)
     e.record()
     torch.cuda.synchronize()
-    us = s.elapsed_time(e) / n_timed * 1e3
+    return s.elapsed_time(e) / n * 1e3
+
+
+def time_dapply(torch, I, lat, prec, nrhs=1, n_warm=10, n_timed=100):
+    """D-apply timing: three input and three output copies rotated so that no
+    launch starts with its operands in cache."""
+    import numpy as np
+    psi = I.gaussian_source(lat.dims, 2, nrhs) if nrhs > 1 else I.gaussian_source(lat.dims, 2)
+    xs = [lat.pack(psi, prec, nrhs) for _ in range(3)]
+    ys = [lat.empty(prec, nrhs) for _ in range(3)]
+    for k in range(n_warm):
+        lat.apply_D(prec, 0.125, 1.0, xs[k % 3], ys[k % 3], nrhs)
+    torch.cuda.synchronize()
+    us = event_time_us(torch, lambda k: lat.apply_D(prec, 0.125, 1.0, xs[k % 3], ys[(k + 1) % 3], nrhs), n_timed)
     del xs, ys
     _ = np
     return us
 
 
+def timed_solves(torch, lat, params, kappa, csw, e, phi, steps, warmup, nrhs=1):
+    for _ in range(warmup):
+        lat.solve_nested(params, kappa, csw, e, phi, nrhs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(steps):
+        _, st = lat.solve_nested(params, kappa, csw, e, phi, nrhs)
+        stats.append(st)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3, stats
+
+
+def ras_desc(p):
+    r = p.ras
+    return {"block": list(r.block), "s": r.s, "n_ras": r.n_ras, "n_dominv": r.n_dominv,
+            "storage": {0: "f64", 1: "f32", 2: "f16"}[r.storage], "tol_inner": p.tol_inner}
+
+
+def stats_desc(st):
+    return {k: st[k] for k in ("outer_iters", "inner_iters", "restarts", "dslash_full", "dslash_block",
+                               "ras_sweeps", "true_resid")}
+
+
+def pct(a, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+def serve_bench(W, I, np, ctx, n_req, slots):
+    """Serving mix: lattices 8^4, 16^3x32, 24^3x48, 32^4 with weights 4:3:2:1,
+    kappa ~ U[0.115, 0.125], c_sw in {1.0, 1.5}, eps = 0.5 gauge fields (seed 1,
+    resident), Gaussian sources with seed 1000 + request id, tolerance 1e-10.
+    The request stream (sizes, couplings, Poisson gaps) is drawn from seed 5.
+    First a closed loop with 2 x slots requests in flight gives the saturated
+    throughput X; then an open loop of Poisson arrivals at rate 0.8 X runs with
+    an HBM budget of 24 GB, so admission by free memory binds."""
+    from concurrent.futures import ThreadPoolExecutor
+    rng = np.random.default_rng(5)
+    w = np.asarray(SERVE_WEIGHTS, dtype=float)
+    kind = rng.choice(len(SERVE_SIZES), size=n_req, p=w / w.sum())
+    kappa = rng.uniform(0.115, 0.125, size=n_req)
+    csw = rng.choice(np.array([1.0, 1.5]), size=n_req)
+    gaps = rng.exponential(1.0, size=n_req)
+    gauges = {}
+    for k, d in enumerate(SERVE_SIZES):
+        gauges[k] = I.random_gauge(d, 0.5, 1)
+    log("serving: gauge fields generated")
+    pool = ThreadPoolExecutor(12)
+
+    def source(i):
+        return I.gaussian_source(SERVE_SIZES[kind[i]], 1000 + int(i))
+
+    def run(budget, arrivals):
+        srv = W.Server(ctx, max_slots=slots, hbm_budget=budget)
+        for k, d in enumerate(SERVE_SIZES):
+            srv.register_gauge(k, d, gauges[k])
+        ahead = 48
+        futs = {i: pool.submit(source, i) for i in range(min(n_req, ahead))}
+        inflight, done = {}, []
+        nxt, late = 0, 0
+        t0 = time.monotonic()
+        window = 2 * slots
+        while len(done) < n_req:
+            while nxt < n_req:
+                if arrivals is None and len(inflight) >= window:
+                    break
+                if arrivals is not None and time.monotonic() < t0 + arrivals[nxt]:
+                    break
+                eta = futs.pop(nxt).result()
+                if nxt + ahead < n_req:
+                    futs[nxt + ahead] = pool.submit(source, nxt + ahead)
+                if arrivals is not None and time.monotonic() > t0 + arrivals[nxt] + 0.005:
+                    late += 1
+                t = srv.submit(int(kind[nxt]), float(kappa[nxt]), float(csw[nxt]), eta)
+                inflight[t] = nxt
+                nxt += 1
+            for t in list(inflight):
+                r = srv.poll(t)
+                if r is not None:
+                    done.append((inflight.pop(t), r[1]))
+            time.sleep(0.0005)
+        T = time.monotonic() - t0
+        srv.close()
+        bad = [i for i, r in done if r["status"] != 0 or not r["converged"] or r["true_resid"] > 1e-10]
+        lat_ms = []
+        for i, r in done:
+            # open loop: latency from the scheduled arrival; closed loop: from submit
+            start = r["t_submit"] if arrivals is None else t0 + arrivals[i]
+            lat_ms.append((r["t_done"] - start) * 1e3)
+        svc_ms = [(r["t_done"] - r["t_admit"]) * 1e3 for _, r in done]
+        wait_ms = [(r["t_admit"] - r["t_submit"]) * 1e3 for _, r in done]
+        per_size = {}
+        for k, d in enumerate(SERVE_SIZES):
+            ls = [lat_ms[j] for j, (i, _) in enumerate(done) if kind[i] == k]
+            per_size["x".join(map(str, d))] = {"n": len(ls), "p50_ms": round(pct(ls, 50), 3) if ls else None,
+                                               "p99_ms": round(pct(ls, 99), 3) if ls else None}
+        return {"requests": n_req, "seconds": round(T, 3), "solves_per_s": round(n_req / T, 3),
+                "p50_ms": round(pct(lat_ms, 50), 3), "p99_ms": round(pct(lat_ms, 99), 3),
+                "service_p50_ms": round(pct(svc_ms, 50), 3), "admission_wait_p99_ms": round(pct(wait_ms, 99), 3),
+                "failed": len(bad), "late_submits": late, "per_size": per_size}
+
+    closed = run(0, None)
+    log(f"serving: closed loop {closed['solves_per_s']} solves/s")
+    lam = 0.8 * closed["solves_per_s"]
+    arrivals = np.cumsum(gaps) / lam
+    opened = run(24 << 30, arrivals)
+    opened["rate_per_s"] = round(lam, 3)
+    opened["hbm_budget_bytes"] = 24 << 30
+    log(f"serving: Poisson p50 {opened['p50_ms']} ms p99 {opened['p99_ms']} ms")
+    pool.shutdown()
+    return {"closed_loop": closed, "poisson": opened, "slots": slots,
+            "mix": {"x".join(map(str, d)): wt for d, wt in zip(SERVE_SIZES, SERVE_WEIGHTS)}}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the solver has no multi-GPU path in this build "
-              "(every domain of the lattice lives on one device); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: every domain of the lattice lives on one device and the library has "
+              "no multi-GPU path; run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -113,54 +247,56 @@ def main():
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
-        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        s.record()
-        for _ in range(5):
-            b.copy_(a)
-        e.record()
-        torch.cuda.synchronize()
-        ms = s.elapsed_time(e) / 5
+        ms = event_time_us(torch, lambda k: b.copy_(a), 5) / 1e3
         print(json.dumps({"mode": "copyref", "bytes_read_per_copy": n, "bytes_written_per_copy": n, "copies": 6,
                           "ms_per_copy": ms, "GBps_read_plus_write": 2 * n / ms / 1e6}))
         return
+    ctx = W.Context(0)
     if args.mode == "dapply":
-        ctx = W.Context(0)
         big = (32, 32, 32, 32)
         lb = W.Lattice(ctx, big)
         lb.upload_gauge(I.random_gauge(big, 1.0, 1))
-        us = time_dapply(W, torch, lb, 1, n_warm=3, n_timed=10)
+        us = time_dapply(torch, I, lb, 1, n_warm=3, n_timed=10)
         print(json.dumps({"mode": "dapply", "V": lb.V, "us": us, "launches": 13}))
         lb.close()
         ctx.close()
         return
+    if args.mode == "serve":
+        print(json.dumps({"mode": "serve", "serving": serve_bench(W, I, np, ctx, args.requests, args.slots)}))
+        ctx.close()
+        return
+
     dims = (16, 16, 16, 32)
     kappa, csw, tol = 0.125, 1.0, 1e-10
-    block = tuple(int(v) for v in args.block.split("x"))
-    s, nd, nras = args.overlap, args.n_dominv, args.n_ras
-    storage = W.F16 if args.storage == "f16" else W.F32
-    ctx = W.Context(0)
     lat = W.Lattice(ctx, dims)
     U = I.random_gauge(dims, 0.5, 1)
     lat.upload_gauge(U)
     eta = I.gaussian_source(dims, 2)
     e = lat.pack(eta, W.F64)
     phi = lat.zeros(W.F64)
-    params = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=100,
-                                 ras=W.RasParams.make(block=block, s=s, n_ras=nras, n_dominv=nd, storage=storage))
+    log("16^3x32 fields resident")
 
-    # ---- nested RAS solve: warmup, then exactly K timed steps
-    for _ in range(args.warmup):
-        lat.solve_nested(params, kappa, csw, e, phi)
-    torch.cuda.synchronize()
+    # ---- autotuner (not timed): domain shape, overlap, storage, sweeps, N_dominv, inner tolerance
+    base = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=100)
     t0 = time.perf_counter()
-    stats = []
-    for _ in range(args.steps):
-        rc, st = lat.solve_nested(params, kappa, csw, e, phi)
-        stats.append(st)
-    torch.cuda.synchronize()
-    T = time.perf_counter() - t0
-    ms_per_step = T / args.steps * 1e3
+    tuned, tuned_ms = W.autotune(lat, base, kappa, csw, e, 1)
+    tune_s = time.perf_counter() - t0
+    log(f"autotuned in {tune_s:.1f} s: {ras_desc(tuned)}")
+
+    # ---- the timed steps: K complete solves with the tuned parameters
+    ms_per_step, stats = timed_solves(torch, lat, tuned, kappa, csw, e, phi, args.steps, args.warmup)
     true_res = max(st["true_resid"] for st in stats)
+    sol = lat.unpack(phi, W.F64)
+    log(f"headline solve {ms_per_step:.3f} ms")
+
+    # ---- the literal 8^4-domain configurations, s = 0 and s = 1
+    literal = {}
+    for s in (0, 1):
+        p = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=100,
+                                ras=W.RasParams.make(block=(8, 8, 8, 8), s=s, n_ras=3, n_dominv=4, storage=W.F32))
+        ms, sts = timed_solves(torch, lat, p, kappa, csw, e, phi, max(2, args.steps // 2), 1)
+        literal[f"8x8x8x8_s{s}"] = {"ms": round(ms, 3), "stats": stats_desc(sts[-1])}
+        log(f"8^4 s={s}: {ms:.3f} ms")
 
     # ---- plain FP64 BiCGStab on the same GPU and input
     for _ in range(args.warmup):
@@ -168,50 +304,115 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        rc, pst = lat.solve_bicgstab_f64(tol, 100000, kappa, csw, e, phi)
+        _, pst = lat.solve_bicgstab_f64(tol, 100000, kappa, csw, e, phi)
     torch.cuda.synchronize()
     plain_ms = (time.perf_counter() - t0) / args.steps * 1e3
+    log(f"plain FP64 {plain_ms:.3f} ms")
+
+    # ---- 12 spin-colour point sources batched in one solve (same lattice)
+    multi = None
+    if not args.no_extra:
+        x0, eta12 = I.point_sources(dims, 3)
+        e12 = lat.pack(eta12, W.F64, 12)
+        phi12 = lat.zeros(W.F64, 12)
+        ms12, st12 = timed_solves(torch, lat, tuned, kappa, csw, e12, phi12, max(2, args.steps // 2), 1, nrhs=12)
+        p1 = lat.pack(eta12[0], W.F64)
+        f1 = lat.zeros(W.F64)
+        ms1, _ = timed_solves(torch, lat, tuned, kappa, csw, p1, f1, max(2, args.steps // 2), 1)
+        multi = {"rhs": 12, "source_site": x0, "ms_per_batch": round(ms12, 3),
+                 "solves_per_s": round(12e3 / ms12, 2), "ms_single_point_source": round(ms1, 3),
+                 "per_rhs_cost_vs_single": round(ms12 / 12 / ms1, 3),
+                 "max_true_resid": st12[-1]["true_resid"], "stats": stats_desc(st12[-1])}
+        del e12, phi12, p1, f1
+        log(f"12 rhs: {ms12:.3f} ms per batch")
     lat.close()
 
-    # ---- D-apply against the HBM roofline at 32^4 (does not fit the 256 MB
-    # Infinity Cache), FP32 as the graded kernel, FP16/FP64 alongside
-    roof = None
-    dapply = {}
+    # ---- D-apply against the HBM roofline at 32^4 (1.4 GB FP64 / 705 MB FP32,
+    # larger than the 256 MB Infinity Cache)
+    roof, dapply, big32 = None, {}, None
+    big = (32, 32, 32, 32)
+    if not args.no_dapply or not args.no_extra:
+        big32 = {1.0: I.random_gauge(big, 1.0, 1)}
     if not args.no_dapply:
-        big = (32, 32, 32, 32)
         lb = W.Lattice(ctx, big)
-        lb.upload_gauge(I.random_gauge(big, 1.0, 1))
+        lb.upload_gauge(big32[1.0])
         for prec in (1, 2, 0):
-            us = time_dapply(W, torch, lb, prec)
+            us = time_dapply(torch, I, lb, prec)
             gbs = DAPPLY_BYTES[prec] * lb.V / us / 1e3
             dapply[{0: "f64", 1: "f32", 2: "f16"}[prec]] = {
                 "us": round(us, 2), "GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
-                "gflops": round(DAPPLY_FLOPS * lb.V / us / 1e3, 1)}
+                "gflops": round(DAPPLY_FLOPS * lb.V / us / 1e3, 1), "bytes_per_site": DAPPLY_BYTES[prec]}
+        us12 = time_dapply(torch, I, lb, 1, nrhs=12, n_warm=3, n_timed=20)
+        gbs12 = DAPPLY_12RHS_BYTES_F32 * lb.V / us12 / 1e3
+        dapply["f32_12rhs"] = {"us": round(us12, 2), "GBps": round(gbs12, 1), "frac": round(gbs12 / HBM_PEAK_GBS, 4),
+                               "gflops": round(12 * DAPPLY_FLOPS * lb.V / us12 / 1e3, 1),
+                               "bytes_per_site": DAPPLY_12RHS_BYTES_F32}
         V = lb.V
         f32 = dapply["f32"]
         tb = measured_traffic(1, V)
         roof = {"bound": "hbm", "achieved": f32["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": f32["frac"], "traffic": tb,
-                "kernel": "k_dslash<F32> (D-apply, 32^4, 672 B/site algorithmic)"}
+                "kernel": "k_dslash<F32> full-lattice D-apply, 32^4, 672 algorithmic B/site x 1048576 sites "
+                          "per launch"}
         lb.close()
+        log(f"D-apply 32^4: {dapply}")
 
-    # ---- CPU baseline: the FP64 oracle's nested RAS solve on the same input
+    # ---- 32^4, eps in {0.3, 1.0}: FP16-storage RAS, autotuned domain shape
+    c3 = None
+    if not args.no_extra:
+        c3 = {}
+        big32[0.3] = I.random_gauge(big, 0.3, 1)
+        eta32 = I.gaussian_source(big, 2)
+        for eps in (0.3, 1.0):
+            lb = W.Lattice(ctx, big)
+            lb.upload_gauge(big32[eps])
+            e32 = lb.pack(eta32, W.F64)
+            f32v = lb.zeros(W.F64)
+            b16 = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=100,
+                                      ras=W.RasParams.make(block=(4, 4, 4, 4), storage=W.F16))
+            t16, _ = W.autotune(lb, b16, kappa, csw, e32, 1)
+            t16.ras.storage = W.F16
+            ms32, st32 = timed_solves(torch, lb, t16, kappa, csw, e32, f32v, 2, 1)
+            lb.solve_bicgstab_f64(tol, 100000, kappa, csw, e32, f32v)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, pst32 = lb.solve_bicgstab_f64(tol, 100000, kappa, csw, e32, f32v)
+            torch.cuda.synchronize()
+            pl32 = (time.perf_counter() - t0) * 1e3
+            c3[f"eps{eps}"] = {"ms": round(ms32, 3), "ras": ras_desc(t16), "stats": stats_desc(st32[-1]),
+                               "plain_f64_ms": round(pl32, 3), "plain_f64_iters": pst32["outer_iters"],
+                               "speedup_vs_plain_f64": round(pl32 / ms32, 3)}
+            lb.close()
+            log(f"32^4 eps={eps}: {ms32:.3f} ms (plain {pl32:.3f} ms)")
+        del big32
+
+    serving = None
+    if not args.no_extra and not args.no_serve:
+        serving = serve_bench(W, I, np, ctx, args.requests, args.slots)
+
+    # ---- CPU baseline: the FP64 oracle's nested RAS solve on the same input and parameters
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import Oracle
         o = Oracle(dims, U)
+        r = tuned.ras
         t0 = time.perf_counter()
-        _, info = o.nested(eta, kappa, csw, tol=tol, tol_inner=1e-4, max_inner=100, ras=True, block=block, s=s,
-                           n_ras=nras, n_dominv=nd)
+        osol, info = o.nested(eta, kappa, csw, tol=tol, tol_inner=tuned.tol_inner, max_inner=100, ras=True,
+                              block=tuple(r.block), s=r.s, n_ras=r.n_ras, n_dominv=r.n_dominv)
         tc = time.perf_counter() - t0
+        # the GPU solution, checked by the oracle's own operator
+        gres = float(np.linalg.norm(eta - o.apply_D(sol, kappa, csw)) / np.linalg.norm(eta))
         cpu = {"value": round(1.0 / tc, 5), "unit": "solves/s", "cores": Oracle.num_threads(), "kind": "oracle",
-               "sample": f"one complete FP64 nested RAS-BiCGStab solve of the same 16^3x32 system "
-                         f"({info['outer_iters']} outer / {info['inner_iters']} inner iterations, {tc:.1f} s)"}
+               "sample": f"one complete FP64 nested RAS-BiCGStab solve of the same 16^3x32 system with the same "
+                         f"RAS parameters ({info['outer_iters']} outer / {info['inner_iters']} inner iterations, "
+                         f"{tc:.1f} s)",
+               "gpu_solution_true_resid_by_oracle": gres}
+        log(f"oracle solve {tc:.1f} s")
 
     st0 = stats[-1]
     out = {
         "metric": METRIC,
-        "value": round(args.steps / T, 3),
+        "value": round(1e3 / ms_per_step, 3),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -220,20 +421,23 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64/f32 (outer FP64, inner and RAS FP32)",
-        "data": "synthetic (seeded random SU(3) gauge field and Gaussian source)",
-        "config": {"workload": "16^3x32 nested RAS-BiCGStab solve to 1e-10",
+        "dtype": "f64/f32 (outer FP64; inner BiCGStab and RAS arithmetic FP32)",
+        "data": "synthetic (seeded random SU(3) gauge field eps=0.5 and Gaussian source)",
+        "config": {"workload": "16^3x32 nested RAS-BiCGStab solve to 1e-10 (kappa 0.125, c_sw 1.0)",
                    "lattice": list(dims), "eps": 0.5, "kappa": kappa, "csw": csw, "rhs": 1,
-                   "ras": {"block": list(block), "s": s, "n_dominv": nd, "n_ras": nras, "storage": args.storage},
-                   "parallelism": "single GPU"},
+                   "ras": ras_desc(tuned), "parallelism": "single GPU"},
         "time_to_solution_ms": round(ms_per_step, 3),
         "true_residual": true_res,
-        "solve_stats": {k: st0[k] for k in ("outer_iters", "inner_iters", "dslash_full", "dslash_block",
-                                             "ras_sweeps")},
+        "solve_stats": stats_desc(st0),
+        "autotune_s": round(tune_s, 2),
         "plain_f64_bicgstab_ms": round(plain_ms, 3),
         "plain_f64_iters": pst["outer_iters"],
         "speedup_vs_plain_f64": round(plain_ms / ms_per_step, 3),
+        "literal_8x8x8x8": literal,
+        "multi_rhs_12": multi,
+        "solve_32x4_f16": c3,
         "dapply_32x4": dapply,
+        "serving": serving,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

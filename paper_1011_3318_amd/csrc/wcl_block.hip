@@ -117,6 +117,41 @@ WCL_DEV void blk_hops(const BlockArgs& a, const f4v* rho, int blk, const int lc[
     }
 }
 
+#ifndef WCL_BLK_PIPE
+#define WCL_BLK_PIPE 1
+#endif
+
+// Workspace index of the neighbour of extended site lc in direction mu
+// (forward or backward), or -1 when the hop leaves Omega' (Dirichlet).
+WCL_DEV int blk_neighbour(const Geom& g, const Blocks& B, const int lc[4], int mu, bool fwd) {
+    int ln[4] = {lc[0], lc[1], lc[2], lc[3]};
+    const int e = B.e[mu];
+    if (fwd) {
+        ln[mu] += 1;
+        if (ln[mu] == e) {
+            if (e != g.L[mu]) return -1;
+            ln[mu] = 0;
+        }
+    } else {
+        ln[mu] -= 1;
+        if (ln[mu] < 0) {
+            if (e != g.L[mu]) return -1;
+            ln[mu] = e - 1;
+        }
+    }
+    return local_index(B, ln);
+}
+
+// rho of workspace site n and rows 0,1 of link U_mu at global site li
+// (ordinary cached loads: every MR step re-reads them)
+template <int GP>
+WCL_DEV void blk_fetch(const BlockArgs& a, const f4v* rho, int base, int n, int mu, int li, float s[24], float u[18]) {
+    if (n >= 0) {
+        ws_load(rho, a.NE, base + n, s);
+        GaugeIO<GP>::template load_raw<false>(a.gauge, a.g.V, mu, li, u);
+    }
+}
+
 // q = D_{Omega'} rho on all extended sites; partials <q, rho>, <q, q> per workgroup
 template <int GP>
 __global__ __launch_bounds__(256) void k_blk_dslash(BlockArgs a) {
@@ -130,20 +165,69 @@ __global__ __launch_bounds__(256) void k_blk_dslash(BlockArgs a) {
         int lc[4], x[4];
         block_site(a.g, a.B, blk, l, lc, x);
         const int gi = geom_index(a.g, x);
-        const int e = blk * a.B.ev + l;
+        const int base = blk * a.B.ev;
+        const int e = base + l;
         const f4v* rho = (const f4v*)a.rho + rhs * a.ws_stride;
-        float r0[24], acc[24];
+        float acc[24];
+        const float mk = (float)(-a.kappa);
+#if WCL_BLK_PIPE
+        // the eight hops (x+, x-, y+, y-, z+, z-, t+, t-), software-pipelined:
+        // hop k+1's neighbour and link are requested before hop k is computed
+        int ni[8], li[8];
+        float ph[8];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            ni[2 * mu] = blk_neighbour(a.g, a.B, lc, mu, true);
+            li[2 * mu] = gi;
+            ph[2 * mu] = (x[mu] == a.g.L[mu] - 1) ? (float)a.g.bc[mu] : 1.f;
+            ni[2 * mu + 1] = blk_neighbour(a.g, a.B, lc, mu, false);
+            int y[4] = {x[0], x[1], x[2], x[3]};
+            y[mu] = x[mu] == 0 ? a.g.L[mu] - 1 : x[mu] - 1;
+            li[2 * mu + 1] = geom_index(a.g, y);
+            ph[2 * mu + 1] = (x[mu] == 0) ? (float)a.g.bc[mu] : 1.f;
+        }
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[k] = 0.f;
+        float s0[24], u0[18], s1[24], u1[18];
+        blk_fetch<GP>(a, rho, base, ni[0], 0, li[0], s0, u0);
+#define WCL_BHOP(K, SC, UC, SN, UN)                                                            \
+    if ((K) < 7) blk_fetch<GP>(a, rho, base, ni[(K) + 1], ((K) + 1) / 2, li[(K) + 1], SN, UN); \
+    if (ni[K] >= 0) hop_compute<(K) / 2, ((K) % 2) == 0>(SC, UC, mk * ph[K], acc);
+        WCL_BHOP(0, s0, u0, s1, u1)
+        WCL_BHOP(1, s1, u1, s0, u0)
+        WCL_BHOP(2, s0, u0, s1, u1)
+        WCL_BHOP(3, s1, u1, s0, u0)
+        WCL_BHOP(4, s0, u0, s1, u1)
+        WCL_BHOP(5, s1, u1, s0, u0)
+        WCL_BHOP(6, s0, u0, s1, u1)
+        WCL_BHOP(7, s1, u1, s0, u0)
+#undef WCL_BHOP
+        float r0[24];
+        ws_load(rho, a.NE, e, r0);
+        {
+            const float ck = (float)(a.csw * a.kappa);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                float c[36], y[12];
+                CloverBlk<GP>::template load<false>(a.clover, a.g.V, gi, b, c);
+                herm6_apply(c, r0 + 12 * b, y);
+#pragma unroll
+                for (int j = 0; j < 12; ++j) acc[12 * b + j] += r0[12 * b + j] + ck * y[j];
+            }
+        }
+#else
+        float r0[24];
         ws_load(rho, a.NE, e, r0);
         {
             float c[72];
             CloverIO<GP>::load(a.clover, a.g.V, gi, c);
             clover_term(c, r0, (float)(a.csw * a.kappa), acc);
         }
-        const float mk = (float)(-a.kappa);
         blk_hops<0, GP>(a, rho, blk, lc, x, gi, mk, acc);
         blk_hops<1, GP>(a, rho, blk, lc, x, gi, mk, acc);
         blk_hops<2, GP>(a, rho, blk, lc, x, gi, mk, acc);
         blk_hops<3, GP>(a, rho, blk, lc, x, gi, mk, acc);
+#endif
         ws_store((f4v*)a.q + rhs * a.ws_stride, a.NE, e, acc);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
@@ -297,8 +381,11 @@ WCL_DEV void rebuild_link(const float u12[12], float u[18]) {
     reconstruct_row2(u);
 }
 
+#ifndef WCL_FUSED_MINWAVES
+#define WCL_FUSED_MINWAVES 2
+#endif
 template <int GP, int SRC, int VP, int NT>
-__global__ __launch_bounds__(NT) void k_blk_fused(BlockArgs a, int write_vj) {
+__global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs a, int write_vj) {
     extern __shared__ float lds[];
     float* s_rho = lds;                 // [24][NT]
     float* s_bwd = lds + 24 * NT;       // [4][12][NT]

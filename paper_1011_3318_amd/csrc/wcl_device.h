@@ -41,6 +41,13 @@ WCL_DEV V ld_nt(const V* p) {
     return *p;
 #endif
 }
+// NT = true: non-temporal; false: ordinary cached load (fields that a
+// kernel reads several times, e.g. the domain operator's links and clover)
+template <bool NT, typename V>
+WCL_DEV V ldx(const V* p) {
+    if constexpr (NT) return ld_nt(p);
+    else return *p;
+}
 template <typename V>
 WCL_DEV void st_nt(V* p, V v) {
 #if WCL_NT_STORES
@@ -163,17 +170,19 @@ template <>
 struct GaugeIO<WCL_F64> {
     using T = double;
     // rows 0,1 only (u[0..11]); row 2 is rebuilt by load() or by the caller
+    template <bool NT = true>
     WCL_DEV static void load_raw(const void* base, int V, int mu, int i, T u[18]) {
         const d2v* p = (const d2v*)base;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            d2v v = ld_nt(p + tix(6 * mu + k, i, 24));
+            d2v v = ldx<NT>(p + tix(6 * mu + k, i, 24));
             u[2 * k] = v.x;
             u[2 * k + 1] = v.y;
         }
     }
+    template <bool NT = true>
     WCL_DEV static void load(const void* base, int V, int mu, int i, T u[18]) {
-        load_raw(base, V, mu, i, u);
+        load_raw<NT>(base, V, mu, i, u);
         reconstruct_row2(u);
     }
 };
@@ -182,19 +191,21 @@ template <>
 struct GaugeIO<WCL_F32> {
     using T = float;
     // rows 0,1 only (u[0..11]); row 2 is rebuilt by load() or by the caller
+    template <bool NT = true>
     WCL_DEV static void load_raw(const void* base, int V, int mu, int i, T u[18]) {
         const f4v* p = (const f4v*)base;
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
-            f4v v = ld_nt(p + tix(3 * mu + g, i, 12));
+            f4v v = ldx<NT>(p + tix(3 * mu + g, i, 12));
             u[4 * g] = v.x;
             u[4 * g + 1] = v.y;
             u[4 * g + 2] = v.z;
             u[4 * g + 3] = v.w;
         }
     }
+    template <bool NT = true>
     WCL_DEV static void load(const void* base, int V, int mu, int i, T u[18]) {
-        load_raw(base, V, mu, i, u);
+        load_raw<NT>(base, V, mu, i, u);
         reconstruct_row2(u);
     }
 };
@@ -203,19 +214,21 @@ template <>
 struct GaugeIO<WCL_F16> {
     using T = float;
     // rows 0,1 only (u[0..11]); row 2 is rebuilt by load() or by the caller
+    template <bool NT = true>
     WCL_DEV static void load_raw(const void* base, int V, int mu, int i, T u[18]) {
         const h4v* p = (const h4v*)base;
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
-            f4v v = __builtin_convertvector(ld_nt(p + tix(3 * mu + g, i, 12)), f4v);
+            f4v v = __builtin_convertvector(ldx<NT>(p + tix(3 * mu + g, i, 12)), f4v);
             u[4 * g] = v.x;
             u[4 * g + 1] = v.y;
             u[4 * g + 2] = v.z;
             u[4 * g + 3] = v.w;
         }
     }
+    template <bool NT = true>
     WCL_DEV static void load(const void* base, int V, int mu, int i, T u[18]) {
-        load_raw(base, V, mu, i, u);
+        load_raw<NT>(base, V, mu, i, u);
         reconstruct_row2(u);
     }
 };
@@ -229,11 +242,12 @@ struct CloverIO;
 template <>
 struct CloverIO<WCL_F64> {
     using T = double;
+    template <bool NT = true>
     WCL_DEV static void load(const void* base, int V, int i, T c[72]) {
         const d2v* p = (const d2v*)base;
 #pragma unroll
         for (int k = 0; k < 36; ++k) {
-            d2v v = ld_nt(p + tix(k, i, 36));
+            d2v v = ldx<NT>(p + tix(k, i, 36));
             c[2 * k] = v.x;
             c[2 * k + 1] = v.y;
         }
@@ -243,11 +257,12 @@ struct CloverIO<WCL_F64> {
 template <>
 struct CloverIO<WCL_F32> {
     using T = float;
+    template <bool NT = true>
     WCL_DEV static void load(const void* base, int V, int i, T c[72]) {
         const f4v* p = (const f4v*)base;
 #pragma unroll
         for (int k = 0; k < 18; ++k) {
-            f4v v = ld_nt(p + tix(k, i, 18));
+            f4v v = ldx<NT>(p + tix(k, i, 18));
             c[4 * k] = v.x;
             c[4 * k + 1] = v.y;
             c[4 * k + 2] = v.z;
@@ -259,16 +274,69 @@ struct CloverIO<WCL_F32> {
 template <>
 struct CloverIO<WCL_F16> {
     using T = float;
+    template <bool NT = true>
     WCL_DEV static void load(const void* base, int V, int i, T c[72]) {
         const h8v* p = (const h8v*)base;
         const float* sc = (const float*)((const char*)base + half_clover_scale_offset(V));
         float s = sc[i];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            f8v v = __builtin_convertvector(ld_nt(p + tix(k, i, 9)), f8v);
+            f8v v = __builtin_convertvector(ldx<NT>(p + tix(k, i, 9)), f8v);
 #pragma unroll
             for (int j = 0; j < 8; ++j) c[8 * k + j] = v[j] * s;
         }
+    }
+};
+
+// Clover block k of 36 reals (packed Hermitian 6x6).
+template <int P>
+struct CloverBlk;
+template <>
+struct CloverBlk<WCL_F64> {
+    template <bool NT = true>
+    WCL_DEV static void load(const void* base, int V, int i, int k, double c[36]) {
+        const d2v* p = (const d2v*)base;
+#pragma unroll
+        for (int q = 0; q < 18; ++q) {
+            d2v v = ldx<NT>(p + tix(18 * k + q, i, 36));
+            c[2 * q] = v.x;
+            c[2 * q + 1] = v.y;
+        }
+    }
+};
+template <>
+struct CloverBlk<WCL_F32> {
+    template <bool NT = true>
+    WCL_DEV static void load(const void* base, int V, int i, int k, float c[36]) {
+        const f4v* p = (const f4v*)base;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            f4v v = ldx<NT>(p + tix(9 * k + q, i, 18));
+            c[4 * q] = v.x;
+            c[4 * q + 1] = v.y;
+            c[4 * q + 2] = v.z;
+            c[4 * q + 3] = v.w;
+        }
+    }
+};
+template <>
+struct CloverBlk<WCL_F16> {
+    // block 0 = reals 0..35 (groups 0..4), block 1 = reals 36..71 (groups 4..8)
+    template <bool NT = true>
+    WCL_DEV static void load(const void* base, int V, int i, int k, float c[36]) {
+        const h8v* p = (const h8v*)base;
+        const float* sc = (const float*)((const char*)base + half_clover_scale_offset(V));
+        const float s = sc[i];
+        const int off = 4 * k;   // first real of the block inside group 4k
+        float t[40];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            f8v v = __builtin_convertvector(ldx<NT>(p + tix(4 * k + q, i, 9)), f8v);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) t[8 * q + j] = v[j] * s;
+        }
+#pragma unroll
+        for (int j = 0; j < 36; ++j) c[j] = off ? t[4 + j] : t[j];
     }
 };
 
@@ -401,6 +469,18 @@ WCL_DEV void clover_term(const T c[72], const T s[24], T ck, T acc[24]) {
 #pragma unroll
         for (int j = 0; j < 12; ++j) acc[12 * k + j] = s[12 * k + j] + ck * y[j];
     }
+}
+
+// One hop from already-loaded data: s = neighbour spinor, u = rows 0,1 of
+// the link (row 2 rebuilt here).  Forward: (1 - gamma_mu) U_mu(x) psi(x+mu);
+// backward: (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu).
+template <int MU, bool FWD, typename T>
+WCL_DEV void hop_compute(const T s[24], T u[18], T f, T acc[24]) {
+    T h[12], w[12];
+    reconstruct_row2(u);
+    spin_project<MU, FWD>(s, h);
+    su3_apply2<!FWD>(u, h, w);
+    spin_accumulate<MU, FWD>(w, f, acc);
 }
 
 // ------------------------------------------------------ XCD remapping ---

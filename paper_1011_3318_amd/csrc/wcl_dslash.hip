@@ -9,18 +9,6 @@
 #include "wcl_device.h"
 #include "wcl_kernels.h"
 
-// One hop from already-loaded data: s = neighbour spinor, u = rows 0,1 of
-// the link (row 2 rebuilt here).  Forward: (1 - gamma_mu) U_mu(x) psi(x+mu);
-// backward: (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu).
-template <int MU, bool FWD, typename T>
-WCL_DEV void hop_compute(const T s[24], T u[18], T f, T acc[24]) {
-    T h[12], w[12];
-    reconstruct_row2(u);
-    spin_project<MU, FWD>(s, h);
-    su3_apply2<!FWD>(u, h, w);
-    spin_accumulate<MU, FWD>(w, f, acc);
-}
-
 // The eight hops in the order (x+, x-, y+, y-, z+, z-, t+, t-): neighbour
 // site, link site and boundary phase of each.
 template <typename T>
@@ -41,9 +29,39 @@ WCL_DEV void hop_sites(const Geom& g, int i, const int x[4], int nbr[8], int lnk
     }
 }
 
-// (D psi)(x).  Software-pipelined: the neighbour spinor and link of hop k+1
-// are requested before hop k is computed (two register buffers), so every
-// wavefront keeps two hops' loads in flight.
+#ifndef WCL_CLOVER_LAST
+#define WCL_CLOVER_LAST 0
+#endif
+#ifndef WCL_PREFETCH_LINK
+#define WCL_PREFETCH_LINK 1
+#endif
+#ifndef WCL_PIPE
+#define WCL_PIPE 1
+#endif
+
+// (D psi)(x).  Software-pipelined: the neighbour spinor (and link) of hop
+// k+1 are requested before hop k is computed (two register buffers), so
+// every wavefront keeps two hops' loads in flight.  The site term A psi is
+// applied either first or last, one 6x6 clover block at a time.
+template <int GP, int SPI, typename T>
+WCL_DEV void clover_site(const DslashArgs& a, const char* in, int i, T acc[24], bool first) {
+    const int V = a.g.V;
+    const T ck = T(a.csw * a.kappa);
+    T s[24];
+    SpinorIO<SPI>::load(in, V, i, s);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        T c[36], y[12];
+        CloverBlk<GP>::load(a.clover, V, i, b, c);
+        herm6_apply(c, s + 12 * b, y);
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+            const T v = s[12 * b + j] + ck * y[j];
+            acc[12 * b + j] = first ? v : acc[12 * b + j] + v;
+        }
+    }
+}
+
 template <int GP, int SPI, typename T>
 WCL_DEV void dslash_site(const DslashArgs& a, const char* in, int i, T acc[24]) {
     const int V = a.g.V;
@@ -51,22 +69,46 @@ WCL_DEV void dslash_site(const DslashArgs& a, const char* in, int i, T acc[24]) 
     T ph[8];
     geom_coords(a.g, i, x);
     hop_sites(a.g, i, x, nbr, lnk, ph);
+    const T mk = T(-a.kappa);
+#if WCL_PIPE == 0
+    if (WCL_CLOVER_LAST) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[k] = T(0);
+    } else {
+        clover_site<GP, SPI>(a, in, i, acc, true);
+    }
+#define WCL_HOP1(K)                                                                \
+    {                                                                              \
+        T s_[24], u_[18];                                                          \
+        SpinorIO<SPI>::load(in, V, nbr[K], s_);                                    \
+        GaugeIO<GP>::load_raw(a.gauge, V, (K) / 2, lnk[K], u_);                    \
+        hop_compute<(K) / 2, ((K) % 2) == 0>(s_, u_, mk * ph[K], acc);            \
+    }
+    WCL_HOP1(0) WCL_HOP1(1) WCL_HOP1(2) WCL_HOP1(3) WCL_HOP1(4) WCL_HOP1(5) WCL_HOP1(6) WCL_HOP1(7)
+#undef WCL_HOP1
+#else
     T s0[24], u0[18], s1[24], u1[18];
     SpinorIO<SPI>::load(in, V, nbr[0], s0);
     GaugeIO<GP>::load_raw(a.gauge, V, 0, lnk[0], u0);
-    {
-        T s[24], c[72];
-        SpinorIO<SPI>::load(in, V, i, s);
-        CloverIO<GP>::load(a.clover, V, i, c);
-        clover_term(c, s, T(a.csw * a.kappa), acc);
+    if (WCL_CLOVER_LAST) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[k] = T(0);
+    } else {
+        clover_site<GP, SPI>(a, in, i, acc, true);
     }
-    const T mk = T(-a.kappa);
+#if WCL_PREFETCH_LINK
 #define WCL_HOP(K, SC, UC, SN, UN)                                                 \
     if ((K) < 7) {                                                                 \
         SpinorIO<SPI>::load(in, V, nbr[(K) + 1], SN);                              \
         GaugeIO<GP>::load_raw(a.gauge, V, ((K) + 1) / 2, lnk[(K) + 1], UN);        \
     }                                                                              \
     hop_compute<(K) / 2, ((K) % 2) == 0>(SC, UC, mk * ph[K], acc);
+#else
+#define WCL_HOP(K, SC, UC, SN, UN)                                                 \
+    if ((K) < 7) SpinorIO<SPI>::load(in, V, nbr[(K) + 1], SN);                     \
+    if ((K) > 0) GaugeIO<GP>::load_raw(a.gauge, V, (K) / 2, lnk[K], UC);          \
+    hop_compute<(K) / 2, ((K) % 2) == 0>(SC, UC, mk * ph[K], acc);
+#endif
     WCL_HOP(0, s0, u0, s1, u1)
     WCL_HOP(1, s1, u1, s0, u0)
     WCL_HOP(2, s0, u0, s1, u1)
@@ -76,6 +118,8 @@ WCL_DEV void dslash_site(const DslashArgs& a, const char* in, int i, T acc[24]) 
     WCL_HOP(6, s0, u0, s1, u1)
     WCL_HOP(7, s1, u1, s0, u0)
 #undef WCL_HOP
+#endif
+    if (WCL_CLOVER_LAST) clover_site<GP, SPI>(a, in, i, acc, false);
 }
 
 template <int GP, int SPI, int SPO, int EPI, int SPY>
@@ -119,55 +163,6 @@ __global__ __launch_bounds__(256, WCL_DSLASH_MINWAVES) void k_dslash(DslashArgs 
 }
 
 // ------------------------------------------------ several lanes per site
-// Clover block k of 36 reals (packed Hermitian 6x6).
-template <int P>
-struct CloverBlk;
-template <>
-struct CloverBlk<WCL_F64> {
-    WCL_DEV static void load(const void* base, int V, int i, int k, double c[36]) {
-        const d2v* p = (const d2v*)base;
-#pragma unroll
-        for (int q = 0; q < 18; ++q) {
-            d2v v = ld_nt(p + tix(18 * k + q, i, 36));
-            c[2 * q] = v.x;
-            c[2 * q + 1] = v.y;
-        }
-    }
-};
-template <>
-struct CloverBlk<WCL_F32> {
-    WCL_DEV static void load(const void* base, int V, int i, int k, float c[36]) {
-        const f4v* p = (const f4v*)base;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            f4v v = ld_nt(p + tix(9 * k + q, i, 18));
-            c[4 * q] = v.x;
-            c[4 * q + 1] = v.y;
-            c[4 * q + 2] = v.z;
-            c[4 * q + 3] = v.w;
-        }
-    }
-};
-template <>
-struct CloverBlk<WCL_F16> {
-    // block 0 = reals 0..35 (groups 0..4), block 1 = reals 36..71 (groups 4..8)
-    WCL_DEV static void load(const void* base, int V, int i, int k, float c[36]) {
-        const h8v* p = (const h8v*)base;
-        const float* sc = (const float*)((const char*)base + half_clover_scale_offset(V));
-        const float s = sc[i];
-        const int off = 4 * k;   // first real of the block inside group 4k
-        float t[40];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            f8v v = __builtin_convertvector(ld_nt(p + tix(4 * k + q, i, 9)), f8v);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) t[8 * q + j] = v[j] * s;
-        }
-#pragma unroll
-        for (int j = 0; j < 36; ++j) c[j] = off ? t[4 + j] : t[j];
-    }
-};
-
 // Stores the float groups of s that belong to `lane` of LPS lanes.
 template <int P>
 struct SpinorPart;

@@ -14,7 +14,8 @@ import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime libwcl.so links against)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libwcl.so")
+# WCL_LIBRARY names another build of the same library (e.g. to compare kernel variants)
+LIB_PATH = os.environ.get("WCL_LIBRARY") or os.path.join(_HERE, "libwcl.so")
 
 F64, F32, F16 = 0, 1, 2
 BLOCK_AUTO, BLOCK_FUSED, BLOCK_SPLIT = 0, 1, 2
