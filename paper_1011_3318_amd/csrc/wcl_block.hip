@@ -374,12 +374,109 @@ WCL_DEV void wg_allreduce3(double d[3], double* sh) {
     }
 }
 
-template <int MU>
-WCL_DEV void rebuild_link(const float u12[12], float u[18]) {
+// Links U_mu(x) (rows 0, 1) and the clover block pair of one site, held in
+// registers for all MR steps: FP32 values for FP32 storage, the stored
+// binary16 words (two per register) for FP16 storage, which halves the
+// register footprint; values are widened to FP32 where they are used.
+template <int GP>
+struct SiteFields {
+    float u[4][12];
+    float c[72];
+    WCL_DEV void zero() {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) u[k] = u12[k];
-    reconstruct_row2(u);
-}
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int k = 0; k < 12; ++k) u[mu][k] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 72; ++k) c[k] = 0.f;
+    }
+    WCL_DEV void load(const BlockArgs& a, int gi) {
+        float t[18];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            GaugeIO<GP>::load_raw(a.gauge, a.g.V, mu, gi, t);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) u[mu][k] = t[k];
+        }
+        CloverIO<GP>::load(a.clover, a.g.V, gi, c);
+    }
+    template <int MU>
+    WCL_DEV void link(float w[18]) const {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) w[k] = u[MU][k];
+        reconstruct_row2(w);
+    }
+    // q = A r = r + ck C r
+    WCL_DEV void site_term(const float r[24], float ck, float q[24]) const { clover_term(c, r, ck, q); }
+};
+
+template <>
+struct SiteFields<WCL_F16> {
+    h2v u[4][6];
+    h2v c[36];
+    float cs;   // clover scale of this site
+    WCL_DEV void zero() {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) u[mu][k] = h2v{0, 0};
+#pragma unroll
+        for (int k = 0; k < 36; ++k) c[k] = h2v{0, 0};
+        cs = 0.f;
+    }
+    WCL_DEV void load(const BlockArgs& a, int gi) {
+        const h4v* pg = (const h4v*)a.gauge;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int g = 0; g < 3; ++g) {
+                const h4v v = ld_nt(pg + tix(3 * mu + g, gi, 12));
+                u[mu][2 * g] = h2v{v.x, v.y};
+                u[mu][2 * g + 1] = h2v{v.z, v.w};
+            }
+        const h8v* pc = (const h8v*)a.clover;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const h8v v = ld_nt(pc + tix(k, gi, 9));
+#pragma unroll
+            for (int j = 0; j < 4; ++j) c[4 * k + j] = h2v{v[2 * j], v[2 * j + 1]};
+        }
+        cs = ((const float*)((const char*)a.clover + half_clover_scale_offset(a.g.V)))[gi];
+    }
+    // the widening is kept inside the step loop: an opaque zero (a fresh
+    // scalar each call) stops the compiler from hoisting the FP32 copies
+    WCL_DEV static h2v opaque(h2v v) {
+        unsigned z;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+        return __builtin_bit_cast(h2v, __builtin_bit_cast(unsigned, v) | z);
+    }
+    template <int MU>
+    WCL_DEV void link(float w[18]) const {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const f2v f = __builtin_convertvector(opaque(u[MU][k]), f2v);
+            w[2 * k] = f.x;
+            w[2 * k + 1] = f.y;
+        }
+        reconstruct_row2(w);
+    }
+    WCL_DEV void site_term(const float r[24], float ck, float q[24]) const {
+        const float f = ck * cs;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            float cb[36], y[12];
+#pragma unroll
+            for (int k = 0; k < 18; ++k) {
+                const f2v v = __builtin_convertvector(opaque(c[18 * b + k]), f2v);
+                cb[2 * k] = v.x;
+                cb[2 * k + 1] = v.y;
+            }
+            herm6_apply(cb, r + 12 * b, y);
+#pragma unroll
+            for (int j = 0; j < 12; ++j) q[12 * b + j] = r[12 * b + j] + f * y[j];
+        }
+    }
+};
 
 #ifndef WCL_FUSED_MINWAVES
 #define WCL_FUSED_MINWAVES 2
@@ -397,7 +494,9 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
     int lc[4] = {0, 0, 0, 0}, x[4] = {0, 0, 0, 0}, gi = 0;
     int nf[4], nb[4];
     float phf[4], phb[4];
-    float rho[24], xs[24], u12[4][12] = {}, c[72] = {};
+    float rho[24], xs[24];
+    SiteFields<GP> F;
+    F.zero();
 #pragma unroll
     for (int k = 0; k < 24; ++k) {
         rho[k] = 0.f;
@@ -407,14 +506,7 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
         block_site(a.g, a.B, blk, l, lc, x);
         gi = geom_index(a.g, x);
         SpinorIO<SRC>::load((const char*)a.src + rhs * a.src_stride, a.g.V, gi, rho);   // projection P r
-        float u[18];
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            GaugeIO<GP>::load(a.gauge, a.g.V, mu, gi, u);
-#pragma unroll
-            for (int k = 0; k < 12; ++k) u12[mu][k] = u[k];
-        }
-        CloverIO<GP>::load(a.clover, a.g.V, gi, c);
+        F.load(a, gi);
     }
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
@@ -450,7 +542,7 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
             for (int k = 0; k < 24; ++k) r[k] = s_rho[k * NT + l];
 #define WCL_BWD(MU)                                                         \
     spin_project<MU, false>(r, h);                                          \
-    rebuild_link<MU>(u12[MU], u);                                           \
+    F.template link<MU>(u);                                                 \
     su3_apply2<true>(u, h, w);                                              \
     _Pragma("unroll") for (int k = 0; k < 12; ++k) s_bwd[(MU * 12 + k) * NT + l] = w[k];
             WCL_BWD(0) WCL_BWD(1) WCL_BWD(2) WCL_BWD(3)
@@ -463,7 +555,7 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
             float r[24];
 #pragma unroll
             for (int k = 0; k < 24; ++k) r[k] = s_rho[k * NT + l];
-            clover_term(c, r, ck, q);
+            F.site_term(r, ck, q);
         }
         {
             float s[24], h[12], w[12], u[18];
@@ -471,7 +563,7 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
     if (nf[MU] >= 0) {                                                                          \
         _Pragma("unroll") for (int k = 0; k < 24; ++k) s[k] = s_rho[k * NT + nf[MU]];         \
         spin_project<MU, true>(s, h);                                                           \
-        rebuild_link<MU>(u12[MU], u);                                                           \
+        F.template link<MU>(u);                                                                 \
         su3_apply2<false>(u, h, w);                                                             \
         spin_accumulate<MU, true>(w, mk * phf[MU], q);                                          \
     }                                                                                           \

@@ -29,22 +29,13 @@ WCL_DEV void hop_sites(const Geom& g, int i, const int x[4], int nbr[8], int lnk
     }
 }
 
-#ifndef WCL_CLOVER_LAST
-#define WCL_CLOVER_LAST 0
-#endif
-#ifndef WCL_PREFETCH_LINK
-#define WCL_PREFETCH_LINK 1
-#endif
-#ifndef WCL_PIPE
-#define WCL_PIPE 1
+#ifndef WCL_PIPE_DEPTH
+#define WCL_PIPE_DEPTH 2
 #endif
 
-// (D psi)(x).  Software-pipelined: the neighbour spinor (and link) of hop
-// k+1 are requested before hop k is computed (two register buffers), so
-// every wavefront keeps two hops' loads in flight.  The site term A psi is
-// applied either first or last, one 6x6 clover block at a time.
+// A psi at site i, one 6x6 clover block at a time: acc = psi + c_sw kappa C psi.
 template <int GP, int SPI, typename T>
-WCL_DEV void clover_site(const DslashArgs& a, const char* in, int i, T acc[24], bool first) {
+WCL_DEV void clover_site(const DslashArgs& a, const char* in, int i, T acc[24]) {
     const int V = a.g.V;
     const T ck = T(a.csw * a.kappa);
     T s[24];
@@ -55,71 +46,45 @@ WCL_DEV void clover_site(const DslashArgs& a, const char* in, int i, T acc[24], 
         CloverBlk<GP>::load(a.clover, V, i, b, c);
         herm6_apply(c, s + 12 * b, y);
 #pragma unroll
-        for (int j = 0; j < 12; ++j) {
-            const T v = s[12 * b + j] + ck * y[j];
-            acc[12 * b + j] = first ? v : acc[12 * b + j] + v;
-        }
+        for (int j = 0; j < 12; ++j) acc[12 * b + j] = s[12 * b + j] + ck * y[j];
     }
 }
 
+// Hops K..7 of a D-deep software pipeline: register slot K % D holds the
+// neighbour spinor and link of hop K (requested D hops earlier); once hop K
+// is computed the slot is refilled with hop K + D, so D - 1 hops' loads are
+// in flight while a hop is computed.
+template <int K, int D, int GP, int SPI, typename T>
+WCL_DEV void hop_chain(const DslashArgs& a, const char* in, const int nbr[8], const int lnk[8], const T ph[8], T mk,
+                       T sb[D][24], T ub[D][18], T acc[24]) {
+    if constexpr (K < 8) {
+        constexpr int slot = K % D;
+        hop_compute<K / 2, (K % 2) == 0>(sb[slot], ub[slot], mk * ph[K], acc);
+        if constexpr (K + D < 8) {
+            SpinorIO<SPI>::load(in, a.g.V, nbr[K + D], sb[slot]);
+            GaugeIO<GP>::load_raw(a.gauge, a.g.V, (K + D) / 2, lnk[K + D], ub[slot]);
+        }
+        hop_chain<K + 1, D, GP, SPI>(a, in, nbr, lnk, ph, mk, sb, ub, acc);
+    }
+}
+
+// (D psi)(x): the site term first, then the eight hops in the order
+// (x+, x-, y+, y-, z+, z-, t+, t-) through the load pipeline.
 template <int GP, int SPI, typename T>
 WCL_DEV void dslash_site(const DslashArgs& a, const char* in, int i, T acc[24]) {
-    const int V = a.g.V;
+    constexpr int D = WCL_PIPE_DEPTH;
     int x[4], nbr[8], lnk[8];
     T ph[8];
     geom_coords(a.g, i, x);
     hop_sites(a.g, i, x, nbr, lnk, ph);
-    const T mk = T(-a.kappa);
-#if WCL_PIPE == 0
-    if (WCL_CLOVER_LAST) {
+    T sb[D][24], ub[D][18];
 #pragma unroll
-        for (int k = 0; k < 24; ++k) acc[k] = T(0);
-    } else {
-        clover_site<GP, SPI>(a, in, i, acc, true);
+    for (int k = 0; k < D; ++k) {
+        SpinorIO<SPI>::load(in, a.g.V, nbr[k], sb[k]);
+        GaugeIO<GP>::load_raw(a.gauge, a.g.V, k / 2, lnk[k], ub[k]);
     }
-#define WCL_HOP1(K)                                                                \
-    {                                                                              \
-        T s_[24], u_[18];                                                          \
-        SpinorIO<SPI>::load(in, V, nbr[K], s_);                                    \
-        GaugeIO<GP>::load_raw(a.gauge, V, (K) / 2, lnk[K], u_);                    \
-        hop_compute<(K) / 2, ((K) % 2) == 0>(s_, u_, mk * ph[K], acc);            \
-    }
-    WCL_HOP1(0) WCL_HOP1(1) WCL_HOP1(2) WCL_HOP1(3) WCL_HOP1(4) WCL_HOP1(5) WCL_HOP1(6) WCL_HOP1(7)
-#undef WCL_HOP1
-#else
-    T s0[24], u0[18], s1[24], u1[18];
-    SpinorIO<SPI>::load(in, V, nbr[0], s0);
-    GaugeIO<GP>::load_raw(a.gauge, V, 0, lnk[0], u0);
-    if (WCL_CLOVER_LAST) {
-#pragma unroll
-        for (int k = 0; k < 24; ++k) acc[k] = T(0);
-    } else {
-        clover_site<GP, SPI>(a, in, i, acc, true);
-    }
-#if WCL_PREFETCH_LINK
-#define WCL_HOP(K, SC, UC, SN, UN)                                                 \
-    if ((K) < 7) {                                                                 \
-        SpinorIO<SPI>::load(in, V, nbr[(K) + 1], SN);                              \
-        GaugeIO<GP>::load_raw(a.gauge, V, ((K) + 1) / 2, lnk[(K) + 1], UN);        \
-    }                                                                              \
-    hop_compute<(K) / 2, ((K) % 2) == 0>(SC, UC, mk * ph[K], acc);
-#else
-#define WCL_HOP(K, SC, UC, SN, UN)                                                 \
-    if ((K) < 7) SpinorIO<SPI>::load(in, V, nbr[(K) + 1], SN);                     \
-    if ((K) > 0) GaugeIO<GP>::load_raw(a.gauge, V, (K) / 2, lnk[K], UC);          \
-    hop_compute<(K) / 2, ((K) % 2) == 0>(SC, UC, mk * ph[K], acc);
-#endif
-    WCL_HOP(0, s0, u0, s1, u1)
-    WCL_HOP(1, s1, u1, s0, u0)
-    WCL_HOP(2, s0, u0, s1, u1)
-    WCL_HOP(3, s1, u1, s0, u0)
-    WCL_HOP(4, s0, u0, s1, u1)
-    WCL_HOP(5, s1, u1, s0, u0)
-    WCL_HOP(6, s0, u0, s1, u1)
-    WCL_HOP(7, s1, u1, s0, u0)
-#undef WCL_HOP
-#endif
-    if (WCL_CLOVER_LAST) clover_site<GP, SPI>(a, in, i, acc, false);
+    clover_site<GP, SPI>(a, in, i, acc);
+    hop_chain<0, D, GP, SPI>(a, in, nbr, lnk, ph, T(-a.kappa), sb, ub, acc);
 }
 
 template <int GP, int SPI, int SPO, int EPI, int SPY>
