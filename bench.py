@@ -48,10 +48,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", default="full", choices=["full", "dapply", "copyref", "serve"],
+    ap.add_argument("--mode", default="full", choices=["full", "dapply", "copyref", "serve", "solve"],
                     help="dapply: only the 32^4 FP32 D-apply loop; copyref: a 1 GiB device copy "
                          "(the reference kernel for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE); serve: only the "
-                         "serving run")
+                         "serving run; solve: K timed 16^3x32 solves with the RAS parameters given below "
+                         "(no autotuning), for kernel traces")
+    ap.add_argument("--block", default="4x4x4x4", help="solve mode: domain shape")
+    ap.add_argument("--overlap", type=int, default=0, help="solve mode: overlap s")
+    ap.add_argument("--storage", default="f16", choices=["f32", "f16"], help="solve mode: RAS storage")
+    ap.add_argument("--n-ras", type=int, default=3)
+    ap.add_argument("--n-dominv", type=int, default=4)
+    ap.add_argument("--tol-inner", type=float, default=1e-4)
+    ap.add_argument("--point-sources", action="store_true", help="solve mode: the 12 point sources in one batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dapply", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 12-source, 32^4 and serving sections")
@@ -268,6 +276,22 @@ def main():
 
     dims = (16, 16, 16, 32)
     kappa, csw, tol = 0.125, 1.0, 1e-10
+    if args.mode == "solve":
+        lat = W.Lattice(ctx, dims)
+        lat.upload_gauge(I.random_gauge(dims, 0.5, 1))
+        nrhs = 12 if args.point_sources else 1
+        src = I.point_sources(dims, 3)[1] if args.point_sources else I.gaussian_source(dims, 2)
+        e = lat.pack(src, W.F64, nrhs)
+        phi = lat.zeros(W.F64, nrhs)
+        p = W.SolverParams.make(tol_outer=tol, tol_inner=args.tol_inner, max_outer=200, max_inner=100,
+                                ras=W.RasParams.make(block=tuple(int(v) for v in args.block.split("x")),
+                                                     s=args.overlap, n_ras=args.n_ras, n_dominv=args.n_dominv,
+                                                     storage=W.F16 if args.storage == "f16" else W.F32))
+        ms, sts = timed_solves(torch, lat, p, kappa, csw, e, phi, args.steps, args.warmup, nrhs)
+        print(json.dumps({"mode": "solve", "ms": ms, "nrhs": nrhs, "ras": ras_desc(p), "stats": stats_desc(sts[-1])}))
+        lat.close()
+        ctx.close()
+        return
     lat = W.Lattice(ctx, dims)
     U = I.random_gauge(dims, 0.5, 1)
     lat.upload_gauge(U)

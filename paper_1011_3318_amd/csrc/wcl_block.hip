@@ -42,6 +42,7 @@ __global__ __launch_bounds__(256) void k_blk_project(BlockArgs a) {
     const int per_rhs = a.B.nblocks * a.wpb;
     const int rhs = blockIdx.x / per_rhs;
     const int blk = (blockIdx.x % per_rhs) / a.wpb;
+    if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
     const int l = (blockIdx.x % a.wpb) * 256 + threadIdx.x;
     if (l >= a.B.ev) return;
     int lc[4], x[4];
@@ -158,6 +159,7 @@ __global__ __launch_bounds__(256) void k_blk_dslash(BlockArgs a) {
     const int per_rhs = a.B.nblocks * a.wpb;
     const int rhs = blockIdx.x / per_rhs;
     const int blk = (blockIdx.x % per_rhs) / a.wpb;
+    if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
     const int wl = blockIdx.x % a.wpb;
     const int l = wl * 256 + threadIdx.x;
     double d[3] = {0, 0, 0};
@@ -249,6 +251,7 @@ __global__ __launch_bounds__(256) void k_blk_update(BlockArgs a, int last) {
     const int per_rhs = a.B.nblocks * a.wpb;
     const int rhs = blockIdx.x / per_rhs;
     const int blk = (blockIdx.x % per_rhs) / a.wpb;
+    if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
     const int l = (blockIdx.x % a.wpb) * 256 + threadIdx.x;
     __shared__ float al[2];
     if (threadIdx.x == 0) {
@@ -375,7 +378,9 @@ WCL_DEV void wg_allreduce3(double d[3], double* sh) {
 }
 
 // Links U_mu(x) (rows 0, 1) and the clover block pair of one site, held in
-// registers for all MR steps: FP32 values for FP32 storage, the stored
+// registers for all MR steps (loaded with cached loads: every sweep of every
+// inner iteration reads them again, and at moderate volumes they stay in the
+// Infinity Cache): FP32 values for FP32 storage, the stored
 // binary16 words (two per register) for FP16 storage, which halves the
 // register footprint; values are widened to FP32 where they are used.
 template <int GP>
@@ -394,11 +399,11 @@ struct SiteFields {
         float t[18];
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
-            GaugeIO<GP>::load_raw(a.gauge, a.g.V, mu, gi, t);
+            GaugeIO<GP>::template load_raw<false>(a.gauge, a.g.V, mu, gi, t);
 #pragma unroll
             for (int k = 0; k < 12; ++k) u[mu][k] = t[k];
         }
-        CloverIO<GP>::load(a.clover, a.g.V, gi, c);
+        CloverIO<GP>::template load<false>(a.clover, a.g.V, gi, c);
     }
     template <int MU>
     WCL_DEV void link(float w[18]) const {
@@ -430,14 +435,14 @@ struct SiteFields<WCL_F16> {
         for (int mu = 0; mu < 4; ++mu)
 #pragma unroll
             for (int g = 0; g < 3; ++g) {
-                const h4v v = ld_nt(pg + tix(3 * mu + g, gi, 12));
+                const h4v v = pg[tix(3 * mu + g, gi, 12)];
                 u[mu][2 * g] = h2v{v.x, v.y};
                 u[mu][2 * g + 1] = h2v{v.z, v.w};
             }
         const h8v* pc = (const h8v*)a.clover;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const h8v v = ld_nt(pc + tix(k, gi, 9));
+            const h8v v = pc[tix(k, gi, 9)];
 #pragma unroll
             for (int j = 0; j < 4; ++j) c[4 * k + j] = h2v{v[2 * j], v[2 * j + 1]};
         }
@@ -489,6 +494,7 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
     __shared__ double s_red[3 * (NT / 64)];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int rhs = lb % a.nrhs, blk = lb / a.nrhs;
+    if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
     const int l = threadIdx.x;
     const bool active = l < a.B.ev;
     int lc[4] = {0, 0, 0, 0}, x[4] = {0, 0, 0, 0}, gi = 0;

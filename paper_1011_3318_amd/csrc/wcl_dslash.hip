@@ -34,7 +34,10 @@ WCL_DEV void hop_sites(const Geom& g, int i, const int x[4], int nbr[8], int lnk
 #endif
 
 // A psi at site i, one 6x6 clover block at a time: acc = psi + c_sw kappa C psi.
-template <int GP, int SPI, typename T>
+// NT: non-temporal loads of the links and clover (fields streamed once per
+// launch); cached loads when the launch's data fits the Infinity Cache or
+// several right-hand sides share the fields.
+template <bool NT, int GP, int SPI, typename T>
 WCL_DEV void clover_site(const DslashArgs& a, const char* in, int i, T acc[24]) {
     const int V = a.g.V;
     const T ck = T(a.csw * a.kappa);
@@ -43,7 +46,7 @@ WCL_DEV void clover_site(const DslashArgs& a, const char* in, int i, T acc[24]) 
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
         T c[36], y[12];
-        CloverBlk<GP>::load(a.clover, V, i, b, c);
+        CloverBlk<GP>::template load<NT>(a.clover, V, i, b, c);
         herm6_apply(c, s + 12 * b, y);
 #pragma unroll
         for (int j = 0; j < 12; ++j) acc[12 * b + j] = s[12 * b + j] + ck * y[j];
@@ -54,7 +57,7 @@ WCL_DEV void clover_site(const DslashArgs& a, const char* in, int i, T acc[24]) 
 // neighbour spinor and link of hop K (requested D hops earlier); once hop K
 // is computed the slot is refilled with hop K + D, so D - 1 hops' loads are
 // in flight while a hop is computed.
-template <int K, int D, int GP, int SPI, typename T>
+template <int K, int D, bool NT, int GP, int SPI, typename T>
 WCL_DEV void hop_chain(const DslashArgs& a, const char* in, const int nbr[8], const int lnk[8], const T ph[8], T mk,
                        T sb[D][24], T ub[D][18], T acc[24]) {
     if constexpr (K < 8) {
@@ -62,15 +65,15 @@ WCL_DEV void hop_chain(const DslashArgs& a, const char* in, const int nbr[8], co
         hop_compute<K / 2, (K % 2) == 0>(sb[slot], ub[slot], mk * ph[K], acc);
         if constexpr (K + D < 8) {
             SpinorIO<SPI>::load(in, a.g.V, nbr[K + D], sb[slot]);
-            GaugeIO<GP>::load_raw(a.gauge, a.g.V, (K + D) / 2, lnk[K + D], ub[slot]);
+            GaugeIO<GP>::template load_raw<NT>(a.gauge, a.g.V, (K + D) / 2, lnk[K + D], ub[slot]);
         }
-        hop_chain<K + 1, D, GP, SPI>(a, in, nbr, lnk, ph, mk, sb, ub, acc);
+        hop_chain<K + 1, D, NT, GP, SPI>(a, in, nbr, lnk, ph, mk, sb, ub, acc);
     }
 }
 
 // (D psi)(x): the site term first, then the eight hops in the order
 // (x+, x-, y+, y-, z+, z-, t+, t-) through the load pipeline.
-template <int GP, int SPI, typename T>
+template <bool NT, int GP, int SPI, typename T>
 WCL_DEV void dslash_site(const DslashArgs& a, const char* in, int i, T acc[24]) {
     constexpr int D = WCL_PIPE_DEPTH;
     int x[4], nbr[8], lnk[8];
@@ -81,13 +84,13 @@ WCL_DEV void dslash_site(const DslashArgs& a, const char* in, int i, T acc[24]) 
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         SpinorIO<SPI>::load(in, a.g.V, nbr[k], sb[k]);
-        GaugeIO<GP>::load_raw(a.gauge, a.g.V, k / 2, lnk[k], ub[k]);
+        GaugeIO<GP>::template load_raw<NT>(a.gauge, a.g.V, k / 2, lnk[k], ub[k]);
     }
-    clover_site<GP, SPI>(a, in, i, acc);
-    hop_chain<0, D, GP, SPI>(a, in, nbr, lnk, ph, T(-a.kappa), sb, ub, acc);
+    clover_site<NT, GP, SPI>(a, in, i, acc);
+    hop_chain<0, D, NT, GP, SPI>(a, in, nbr, lnk, ph, T(-a.kappa), sb, ub, acc);
 }
 
-template <int GP, int SPI, int SPO, int EPI, int SPY>
+template <int GP, int SPI, int SPO, int EPI, int SPY, bool NT>
 #ifndef WCL_DSLASH_MINWAVES
 #define WCL_DSLASH_MINWAVES 1
 #endif
@@ -96,11 +99,12 @@ __global__ __launch_bounds__(256, WCL_DSLASH_MINWAVES) void k_dslash(DslashArgs 
     static_assert((GP == WCL_F64) == (SPI == WCL_F64), "FP64 arithmetic needs FP64 spinors and links");
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int rhs = lb % a.nrhs;
+    if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
     const int i = (lb / a.nrhs) * 256 + threadIdx.x;
     const bool active = i < a.g.V;
     T acc[24];
     if (active) {
-        dslash_site<GP, SPI>(a, (const char*)a.in + rhs * a.in_stride, i, acc);
+        dslash_site<NT, GP, SPI>(a, (const char*)a.in + rhs * a.in_stride, i, acc);
         if (EPI == DS_AXPY) {
             T y[24];
             SpinorIO<SPY>::load((const char*)a.y + rhs * a.y_stride, a.g.V, i, y);
@@ -182,6 +186,7 @@ __global__ __launch_bounds__(256) void k_dslash_ml(DslashArgs a) {
     constexpr int SPW = 256 / LPS, DPL = 4 / LPS;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int rhs = lb % a.nrhs;
+    if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
     const int tile = lb / a.nrhs;
     const int lane = threadIdx.x % LPS;
     const int i = tile * SPW + threadIdx.x / LPS;
@@ -271,13 +276,24 @@ __global__ __launch_bounds__(256) void k_dslash_ml(DslashArgs a) {
     }
 }
 
+static size_t dslash_launch_bytes(int V, int gp, int spi, int spo) {
+    return gauge_bytes(gp, V) + clover_bytes(gp, V) + spinor_rhs_bytes(spi, V) + spinor_rhs_bytes(spo, V);
+}
+
 template <int GP, int SPI, int SPO, int EPI, int SPY>
 static int launch_t(const DslashArgs& a, hipStream_t st) {
     const int tiles = dslash_partials_per_rhs(a.g.V, a.lps);
     switch (a.lps) {
         case 2: k_dslash_ml<GP, SPI, SPO, EPI, SPY, 2><<<tiles * a.nrhs, 256, 0, st>>>(a); break;
         case 4: k_dslash_ml<GP, SPI, SPO, EPI, SPY, 4><<<tiles * a.nrhs, 256, 0, st>>>(a); break;
-        default: k_dslash<GP, SPI, SPO, EPI, SPY><<<tiles * a.nrhs, 256, 0, st>>>(a); break;
+        default:
+            // non-temporal field loads only for one rhs streaming more than the
+            // 256 MB Infinity Cache holds
+            if (a.nrhs == 1 && dslash_launch_bytes(a.g.V, GP, SPI, SPO) > (256u << 20))
+                k_dslash<GP, SPI, SPO, EPI, SPY, true><<<tiles * a.nrhs, 256, 0, st>>>(a);
+            else
+                k_dslash<GP, SPI, SPO, EPI, SPY, false><<<tiles * a.nrhs, 256, 0, st>>>(a);
+            break;
     }
     WCL_HIP(hipGetLastError());
     return WCL_OK;

@@ -5,6 +5,13 @@
 
 enum { DS_PLAIN = 0, DS_AXPY = 1, DS_DOT = 2 };
 
+// BiCGStab scalars of one right-hand side, resident on the device.
+struct Scal {
+    double rho[2], rho_old[2], alpha[2], omega[2], rv[2];
+    double tt, rr, rr0, pp;
+    int active, breakdown;
+};
+
 struct DslashArgs {
     Geom g;
     const void* gauge;
@@ -18,6 +25,7 @@ struct DslashArgs {
     int nrhs;
     int lps;             // lanes per site: 1, 2 or 4
     double* partial;     // DS_DOT: [nrhs][tiles][3]
+    const Scal* sc;      // optional: right-hand sides with sc[rhs].active == 0 are skipped
 };
 
 int launch_pack_spinor(const Geom& g, int prec, int nrhs, const double* aos, void* soa, size_t stride,
@@ -33,12 +41,6 @@ int dslash_partials_per_rhs(int V, int lps);
 int launch_dslash(const DslashArgs& a, int gp, int spi, int spo, int epi, int spy, hipStream_t st);
 
 // ------------------------------------------------------------- solvers --
-// BiCGStab scalars of one right-hand side, resident on the device.
-struct Scal {
-    double rho[2], rho_old[2], alpha[2], omega[2], rv[2];
-    double tt, rr, rr0, pp;
-    int active, breakdown;
-};
 enum { FIN_ALPHA = 0, FIN_OMEGA = 1, FIN_RHO = 2, FIN_PP = 3, FIN_RR = 4, FIN_RR0 = 5 };
 
 int blas_partials(int prec, int64_t V);
@@ -77,6 +79,7 @@ struct BlockArgs {
     double kappa, csw;
     int nrhs;
     double* partial;     // [rhs][nblocks][wpb][3]
+    const Scal* sc;      // optional: right-hand sides with sc[rhs].active == 0 are skipped
 };
 
 int launch_blk_project(const BlockArgs& a, int src_prec, hipStream_t st);

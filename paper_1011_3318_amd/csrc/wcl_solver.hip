@@ -184,8 +184,10 @@ static int pick_kernel(const Blocks& B, int requested, bool* fused) {
     return WCL_OK;
 }
 
+// sc (optional): device scalars of the calling solver; inactive rhs are skipped.
 static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int storage, int kernel, double kappa,
-                     double csw, const void* r, void* v, int nrhs, hipStream_t st, wcl_solve_stats* stats) {
+                     double csw, const void* r, void* v, int nrhs, hipStream_t st, wcl_solve_stats* stats,
+                     const Scal* sc = nullptr) {
     const int64_t V = lat->V;
     const size_t s32 = spinor_rhs_bytes(WCL_F32, V), sst = spinor_rhs_bytes(storage, V);
     bool fused = false;
@@ -204,6 +206,7 @@ static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int stora
     a.nrhs = nrhs;
     a.out = v;
     a.out_stride = s32;
+    a.sc = sc;
     const size_t wsb = (size_t)16 * 6 * NE * nrhs;
     if (!fused) WCL_CHECK(ws->get("ras.rho", wsb, &a.rho));
     if (!fused) WCL_CHECK(ws->get("ras.q", wsb, &a.q));
@@ -250,6 +253,7 @@ static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int stora
             d.csw = csw;
             d.nrhs = nrhs;
             d.lps = lat->lps;
+            d.sc = sc;
             WCL_CHECK(launch_dslash(d, storage, storage, storage, DS_AXPY, src_prec, st));
             if (stats) stats->dslash_full += nrhs;
         }
@@ -328,6 +332,7 @@ struct Engine {
         x.nrhs = nrhs;
         x.lps = lat->lps;
         x.partial = partial;
+        x.sc = d;
         if (stats) stats->dslash_full += nrhs;
         return launch_dslash(x, gp, P, P, DS_DOT, P, st);
     }
@@ -572,8 +577,8 @@ int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, 
     const size_t v32 = spinor_rhs_bytes(WCL_F32, lat->V) * nrhs;
     WCL_CHECK(ws->get("nest.b32", v32, &b32));
     WCL_CHECK(ws->get("nest.y32", v32, &y32));
-    Precond Kras = [&](const void* in, void* out, Scal*, const std::vector<int>&) -> int {
-        return ras_apply(lat, ws, B, storage, prm->ras.kernel, kappa, csw, in, out, nrhs, st, S);
+    Precond Kras = [&](const void* in, void* out, Scal* sc, const std::vector<int>&) -> int {
+        return ras_apply(lat, ws, B, storage, prm->ras.kernel, kappa, csw, in, out, nrhs, st, S, sc);
     };
     Engine outer{lat, ws, "out", WCL_F64, WCL_F64, nrhs, kappa, csw, st, S};
     int outer_partials_G = blas_partials(WCL_F64, lat->V);
