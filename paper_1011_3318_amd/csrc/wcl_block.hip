@@ -378,11 +378,9 @@ WCL_DEV void wg_allreduce3(double d[3], double* sh) {
 }
 
 // Links U_mu(x) (rows 0, 1) and the clover block pair of one site, held in
-// registers for all MR steps (loaded with cached loads: every sweep of every
+// registers (as FP32) for all MR steps.  Cached loads: every sweep of every
 // inner iteration reads them again, and at moderate volumes they stay in the
-// Infinity Cache): FP32 values for FP32 storage, the stored
-// binary16 words (two per register) for FP16 storage, which halves the
-// register footprint; values are widened to FP32 where they are used.
+// Infinity Cache.
 template <int GP>
 struct SiteFields {
     float u[4][12];
@@ -413,74 +411,6 @@ struct SiteFields {
     }
     // q = A r = r + ck C r
     WCL_DEV void site_term(const float r[24], float ck, float q[24]) const { clover_term(c, r, ck, q); }
-};
-
-template <>
-struct SiteFields<WCL_F16> {
-    h2v u[4][6];
-    h2v c[36];
-    float cs;   // clover scale of this site
-    WCL_DEV void zero() {
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-            for (int k = 0; k < 6; ++k) u[mu][k] = h2v{0, 0};
-#pragma unroll
-        for (int k = 0; k < 36; ++k) c[k] = h2v{0, 0};
-        cs = 0.f;
-    }
-    WCL_DEV void load(const BlockArgs& a, int gi) {
-        const h4v* pg = (const h4v*)a.gauge;
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-            for (int g = 0; g < 3; ++g) {
-                const h4v v = pg[tix(3 * mu + g, gi, 12)];
-                u[mu][2 * g] = h2v{v.x, v.y};
-                u[mu][2 * g + 1] = h2v{v.z, v.w};
-            }
-        const h8v* pc = (const h8v*)a.clover;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const h8v v = pc[tix(k, gi, 9)];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) c[4 * k + j] = h2v{v[2 * j], v[2 * j + 1]};
-        }
-        cs = ((const float*)((const char*)a.clover + half_clover_scale_offset(a.g.V)))[gi];
-    }
-    // the widening is kept inside the step loop: an opaque zero (a fresh
-    // scalar each call) stops the compiler from hoisting the FP32 copies
-    WCL_DEV static h2v opaque(h2v v) {
-        unsigned z;
-        asm volatile("s_mov_b32 %0, 0" : "=s"(z));
-        return __builtin_bit_cast(h2v, __builtin_bit_cast(unsigned, v) | z);
-    }
-    template <int MU>
-    WCL_DEV void link(float w[18]) const {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const f2v f = __builtin_convertvector(opaque(u[MU][k]), f2v);
-            w[2 * k] = f.x;
-            w[2 * k + 1] = f.y;
-        }
-        reconstruct_row2(w);
-    }
-    WCL_DEV void site_term(const float r[24], float ck, float q[24]) const {
-        const float f = ck * cs;
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            float cb[36], y[12];
-#pragma unroll
-            for (int k = 0; k < 18; ++k) {
-                const f2v v = __builtin_convertvector(opaque(c[18 * b + k]), f2v);
-                cb[2 * k] = v.x;
-                cb[2 * k + 1] = v.y;
-            }
-            herm6_apply(cb, r + 12 * b, y);
-#pragma unroll
-            for (int j = 0; j < 12; ++j) q[12 * b + j] = r[12 * b + j] + f * y[j];
-        }
-    }
 };
 
 #ifndef WCL_FUSED_MINWAVES
@@ -591,7 +521,9 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
                 d[2] += (double)(qr * qr + qi * qi);
             }
         }
-        // every thread has finished reading rho and the backward terms after this barrier
+        // every thread has finished reading its neighbours' rho and backward
+        // terms after this barrier; the next reads of them follow the next
+        // step's publish barrier, so the update below needs no barrier of its own
         wg_allreduce3<NT / 64>(d, s_red);
         const float ar = d[2] > 0 ? (float)(d[0] / d[2]) : 0.f;
         const float ai = d[2] > 0 ? (float)(d[1] / d[2]) : 0.f;
@@ -603,7 +535,6 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
             s_rho[(2 * k) * NT + l] = pr - (ar * q[2 * k] - ai * q[2 * k + 1]);
             s_rho[(2 * k + 1) * NT + l] = pi - (ar * q[2 * k + 1] + ai * q[2 * k]);
         }
-        __syncthreads();
     }
     // restriction to the owned sites and sum into the output
     if (!active || !block_owned(a.B, lc)) return;

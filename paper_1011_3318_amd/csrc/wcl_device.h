@@ -9,8 +9,6 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 typedef float f8v __attribute__((ext_vector_type(8)));
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef _Float16 h4v __attribute__((ext_vector_type(4)));
-typedef _Float16 h2v __attribute__((ext_vector_type(2)));
-typedef float f2v __attribute__((ext_vector_type(2)));
 typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 
 #define WCL_DEV __device__ __forceinline__
