@@ -48,11 +48,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", default="full", choices=["full", "dapply", "copyref", "serve", "solve"],
+    ap.add_argument("--mode", default="full", choices=["full", "dapply", "copyref", "serve", "solve", "sweep"],
                     help="dapply: only the 32^4 FP32 D-apply loop; copyref: a 1 GiB device copy "
                          "(the reference kernel for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE); serve: only the "
                          "serving run; solve: K timed 16^3x32 solves with the RAS parameters given below "
-                         "(no autotuning), for kernel traces")
+                         "(no autotuning), for kernel traces; sweep: 55 launches of one RAS sweep (NRAS = 1) of the "
+                         "on-chip domain solver with those parameters, for counters")
     ap.add_argument("--block", default="4x4x4x4", help="solve mode: domain shape")
     ap.add_argument("--overlap", type=int, default=0, help="solve mode: overlap s")
     ap.add_argument("--storage", default="f16", choices=["f32", "f16"], help="solve mode: RAS storage")
@@ -69,28 +70,57 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_hash() -> str:
+DAPPLY_SOURCES = ("wcl_dslash.hip", "wcl_device.h", "wcl_internal.h")
+DOMAIN_SOURCES = ("wcl_block.hip", "wcl_device.h", "wcl_internal.h")
+# FP32 VALU peak without packed-FP32 instructions (the library is built
+# without them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
+VALU_F32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# flops of the Wilson-clover operator per site: site term (two 6x6 Hermitian
+# mat-vecs + the combination) and one hop (projection, two SU(3) mat-vecs,
+# accumulation); 552 + 8 x 165 = 1872
+SITE_TERM_FLOPS, HOP_FLOPS = 552, 165
+# one minimal-residual step besides q = D rho: <q, rho>, <q, q>, x += a rho, rho -= a q
+MR_FLOPS = 96 + 48 + 96 + 96
+
+
+def source_hash(files) -> str:
     h = hashlib.sha256()
-    for f in ("wcl_dslash.hip", "wcl_device.h", "wcl_internal.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1011_3318_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(prec: int, V: int):
-    """HBM bytes per launch from the rocprofv3 FETCH_SIZE/WRITE_SIZE runs,
-    scaled by the copy-kernel factor, if they were taken on the current
-    kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "dapply_counters.json")
+def kernel_source_hash() -> str:
+    return source_hash(DAPPLY_SOURCES)
+
+
+def measured_traffic(name: str, files, key: str, V: int):
+    """HBM bytes per launch from the rocprofv3 FETCH_SIZE/WRITE_SIZE runs
+    stored in profiles/<name>, scaled by the copy-kernel factor, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    ent = rec.get(str(prec))
-    if not ent or rec.get("source_hash") != kernel_source_hash() or ent.get("V") != V:
+    ent = rec.get(key)
+    if not ent or rec.get("source_hash") != source_hash(files) or ent.get("V") != V:
         return None
     return ent.get("bytes_per_launch")
+
+
+def domain_sweep_flops(dims, ras, nblocks, ev):
+    """Algorithmic flops of one sweep of the domain solver: N_dominv MR steps
+    on every extended site, each the Dirichlet domain operator (only the hops
+    that stay inside the extended domain) plus the MR vector work."""
+    hops = 0.0
+    for mu in range(4):
+        e = ras.block[mu] + (2 * ras.s if ras.block[mu] < dims[mu] else 0)
+        hops += 2.0 * ((e - 1) / e if e < dims[mu] else 1.0)
+    per_site = SITE_TERM_FLOPS + HOP_FLOPS * hops + MR_FLOPS
+    return per_site * nblocks * ev * ras.n_dominv
 
 
 def event_time_us(torch, fn, n):
@@ -131,6 +161,22 @@ def timed_solves(torch, lat, params, kappa, csw, e, phi, steps, warmup, nrhs=1):
         stats.append(st)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps * 1e3, stats
+
+
+def time_domain_sweep(torch, W, lat, dims, ras, eta, kappa, csw, n=50):
+    """Average duration (HIP events) of one launch of the on-chip domain
+    solver: ras_precondition with NRAS = 1 is exactly one k_blk_fused launch
+    (projection of the FP32 residual, N_dominv MR steps, restriction)."""
+    nb, ev = lat.block_info(ras)
+    one = W.RasParams.make(block=tuple(ras.block), s=ras.s, n_ras=1, n_dominv=ras.n_dominv, storage=ras.storage,
+                           kernel=W.BLOCK_FUSED)
+    r32 = lat.pack(eta, W.F32)
+    v32 = lat.empty(W.F32)
+    for _ in range(5):
+        lat.ras_precondition(one, kappa, csw, r32, v32)
+    torch.cuda.synchronize()
+    us = event_time_us(torch, lambda k: lat.ras_precondition(one, kappa, csw, r32, v32), n)
+    return us, domain_sweep_flops(dims, ras, nb, ev)
 
 
 def ras_desc(p):
@@ -276,6 +322,17 @@ def main():
 
     dims = (16, 16, 16, 32)
     kappa, csw, tol = 0.125, 1.0, 1e-10
+    if args.mode == "sweep":
+        lat = W.Lattice(ctx, dims)
+        lat.upload_gauge(I.random_gauge(dims, 0.5, 1))
+        eta = I.gaussian_source(dims, 2)
+        ras = W.RasParams.make(block=tuple(int(v) for v in args.block.split("x")), s=args.overlap,
+                               n_dominv=args.n_dominv, storage=W.F16 if args.storage == "f16" else W.F32)
+        us, fl = time_domain_sweep(torch, W, lat, dims, ras, eta, kappa, csw)
+        print(json.dumps({"mode": "sweep", "us": us, "flops": fl, "ras": ras_desc(W.SolverParams.make(ras=ras))}))
+        lat.close()
+        ctx.close()
+        return
     if args.mode == "solve":
         lat = W.Lattice(ctx, dims)
         lat.upload_gauge(I.random_gauge(dims, 0.5, 1))
@@ -312,6 +369,22 @@ def main():
     true_res = max(st["true_resid"] for st in stats)
     sol = lat.unpack(phi, W.F64)
     log(f"headline solve {ms_per_step:.3f} ms")
+
+    # ---- the dominant kernel of the step: the on-chip domain solver, one
+    # sweep (NRAS = 1) of the tuned domains, timed with HIP events
+    roof_dom = None
+    nb, ev = lat.block_info(tuned.ras)
+    if ev <= 256:   # the fused (on-chip) domain solver
+        us_dom, fl = time_domain_sweep(torch, W, lat, dims, tuned.ras, eta, kappa, csw)
+        tf = fl / us_dom / 1e6
+        key = "fused_" + "x".join(map(str, tuned.ras.block)) + f"_s{tuned.ras.s}_nd{tuned.ras.n_dominv}_" + \
+              {1: "f32", 2: "f16"}[tuned.ras.storage]
+        roof_dom = {"bound": "alu", "achieved": round(tf, 2), "peak": round(VALU_F32_PEAK_TFLOPS, 1),
+                    "unit": "TFLOP/s", "frac": round(tf / VALU_F32_PEAK_TFLOPS, 4),
+                    "traffic": measured_traffic("domain_counters.json", DOMAIN_SOURCES, key, lat.V),
+                    "kernel": f"k_blk_fused (one RAS sweep: {nb} domains x {ev} sites x {tuned.ras.n_dominv} MR steps "
+                              f"on chip, {fl / 1e9:.3f} GFLOP per launch)", "us_per_launch": round(us_dom, 2)}
+        log(f"domain sweep {us_dom:.1f} us, {tf:.1f} TFLOP/s")
 
     # ---- the literal 8^4-domain configurations, s = 0 and s = 1
     literal = {}
@@ -373,11 +446,11 @@ def main():
                                "bytes_per_site": DAPPLY_12RHS_BYTES_F32}
         V = lb.V
         f32 = dapply["f32"]
-        tb = measured_traffic(1, V)
+        tb = measured_traffic("dapply_counters.json", DAPPLY_SOURCES, "1", V)
         roof = {"bound": "hbm", "achieved": f32["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": f32["frac"], "traffic": tb,
                 "kernel": "k_dslash<F32> full-lattice D-apply, 32^4, 672 algorithmic B/site x 1048576 sites "
-                          "per launch"}
+                          "per launch", "us_per_launch": f32["us"]}
         lb.close()
         log(f"D-apply 32^4: {dapply}")
 
@@ -462,7 +535,8 @@ def main():
         "solve_32x4_f16": c3,
         "dapply_32x4": dapply,
         "serving": serving,
-        "roofline": roof,
+        "roofline": roof_dom,
+        "roofline_dapply": roof,
         "cpu_baseline": cpu,
     }
     ctx.close()
