@@ -329,6 +329,7 @@ def main():
         ras = W.RasParams.make(block=tuple(int(v) for v in args.block.split("x")), s=args.overlap,
                                n_dominv=args.n_dominv, storage=W.F16 if args.storage == "f16" else W.F32)
         us, fl = time_domain_sweep(torch, W, lat, dims, ras, eta, kappa, csw)
+        ras.n_ras = 1
         print(json.dumps({"mode": "sweep", "us": us, "flops": fl, "ras": ras_desc(W.SolverParams.make(ras=ras))}))
         lat.close()
         ctx.close()
