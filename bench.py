@@ -48,12 +48,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", default="full", choices=["full", "dapply", "copyref", "serve", "solve", "sweep"],
+    ap.add_argument("--mode", default="full", choices=["full", "dapply", "copyref", "serve", "solve", "sweep", "paper"],
                     help="dapply: only the 32^4 FP32 D-apply loop; copyref: a 1 GiB device copy "
                          "(the reference kernel for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE); serve: only the "
                          "serving run; solve: K timed 16^3x32 solves with the RAS parameters given below "
                          "(no autotuning), for kernel traces; sweep: 55 launches of one RAS sweep (NRAS = 1) of the "
-                         "on-chip domain solver with those parameters, for counters")
+                         "on-chip domain solver with those parameters, for counters; paper: the paper's 32^4 "
+                         "x-split table with the NRAS x N_dominv scan")
     ap.add_argument("--block", default="4x4x4x4", help="solve mode: domain shape")
     ap.add_argument("--overlap", type=int, default=0, help="solve mode: overlap s")
     ap.add_argument("--storage", default="f16", choices=["f32", "f16"], help="solve mode: RAS storage")
@@ -65,6 +66,9 @@ def parse():
     ap.add_argument("--no-dapply", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 12-source, 32^4 and serving sections")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper's 32^4 x-split table")
+    ap.add_argument("--paper-eps", type=float, default=0.3, help="paper mode: gauge-field eps")
+    ap.add_argument("--paper-scan", action="store_true", help="paper mode: add the NRAS x N_dominv scan")
     ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="serving: concurrent solve slots")
     return ap.parse_args()
@@ -177,6 +181,64 @@ def time_domain_sweep(torch, W, lat, dims, ras, eta, kappa, csw, n=50):
     torch.cuda.synchronize()
     us = event_time_us(torch, lambda k: lat.ras_precondition(one, kappa, csw, r32, v32), n)
     return us, domain_sweep_flops(dims, ras, nb, ev)
+
+
+def paper_table(torch, W, ctx, dims, U, eta, kappa=0.126, csw=1.0, tol=1e-14, n_ras=3, n_dominv=5, scan=False):
+    """The paper's benchmark (Sec. 5, Table 1) on one GPU: 32^4 lattice,
+    kappa 0.126, c_SW 1.0, |eta - D phi|/|eta| < 1e-14, the nested solver
+    without preconditioner and with RAS on the x-only split into 8 domains
+    (L_x/8 x L_y x L_z x L_t) with overlap depth d = 2s = 0, 2, 4, NRAS = 3,
+    N_dominv = 5.  Reports time, the full-lattice D count and the domain work;
+    with scan=True also the NRAS x N_dominv scan of d = 0."""
+    lat = W.Lattice(ctx, dims)
+    lat.upload_gauge(U)
+    e = lat.pack(eta, W.F64)
+    phi = lat.zeros(W.F64)
+    xb = (dims[0] // 8, dims[1], dims[2], dims[3])
+    out = {"lattice": list(dims), "kappa": kappa, "csw": csw, "tol": tol, "domains": list(xb),
+           "n_ras": n_ras, "n_dominv": n_dominv}
+
+    def run(p):
+        lat.solve_nested(p, kappa, csw, e, phi, raise_on_notconv=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = lat.solve_nested(p, kappa, csw, e, phi, raise_on_notconv=False)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, st
+
+    base = dict(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=1000)
+    ms, st = run(W.SolverParams.make(precond=W.PRECOND_NONE, **base))
+    out["no_prec"] = {"ms": round(ms, 3), "dv_count": st["dslash_full"], "outer_iters": st["outer_iters"],
+                      "inner_iters": st["inner_iters"], "true_resid": st["true_resid"],
+                      "converged": bool(st["converged"])}
+    for s in (0, 1, 2):
+        ras = W.RasParams.make(block=xb, s=s, n_ras=n_ras, n_dominv=n_dominv, storage=W.F32)
+        ms, st = run(W.SolverParams.make(ras=ras, **base))
+        # the domain solver alone: one sweep timed with HIP events, times the sweeps of the solve
+        one = W.RasParams.make(block=xb, s=s, n_ras=1, n_dominv=n_dominv, storage=W.F32)
+        r32 = lat.pack(eta, W.F32)
+        v32 = lat.empty(W.F32)
+        lat.ras_precondition(one, kappa, csw, r32, v32)
+        torch.cuda.synchronize()
+        us_sweep = event_time_us(torch, lambda k: lat.ras_precondition(one, kappa, csw, r32, v32), 5)
+        out[f"ras_d{2 * s}"] = {"ms": round(ms, 3), "dv_count": st["dslash_full"], "outer_iters": st["outer_iters"],
+                                "inner_iters": st["inner_iters"], "ras_sweeps": st["ras_sweeps"],
+                                "domain_mr_steps": st["dslash_block"], "true_resid": st["true_resid"],
+                                "converged": bool(st["converged"]),
+                                "dominv_ms_est": round(us_sweep * st["ras_sweeps"] / 1e3, 3)}
+        del r32, v32
+    if scan:
+        grid = {}
+        for nr in range(1, 11):
+            for nd in (1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 20):
+                ras = W.RasParams.make(block=xb, s=0, n_ras=nr, n_dominv=nd, storage=W.F32)
+                ms, st = run(W.SolverParams.make(ras=ras, **base))
+                grid[f"{nr}x{nd}"] = {"ms": round(ms, 3), "dv_count": st["dslash_full"],
+                                      "converged": bool(st["converged"])}
+        best = min((k for k in grid if grid[k]["converged"]), key=lambda k: grid[k]["ms"])
+        out["scan_d0"] = {"best": best, "grid": grid}
+    lat.close()
+    return out
 
 
 def ras_desc(p):
@@ -313,6 +375,14 @@ def main():
         us = time_dapply(torch, I, lb, 1, n_warm=3, n_timed=10)
         print(json.dumps({"mode": "dapply", "V": lb.V, "us": us, "launches": 13}))
         lb.close()
+        ctx.close()
+        return
+    if args.mode == "paper":
+        big = (32, 32, 32, 32)
+        tab = paper_table(torch, W, ctx, big, I.random_gauge(big, args.paper_eps, 1), I.gaussian_source(big, 2),
+                          scan=args.paper_scan)
+        tab["eps"] = args.paper_eps
+        print(json.dumps({"mode": "paper", "paper_table1": tab}))
         ctx.close()
         return
     if args.mode == "serve":
@@ -482,7 +552,13 @@ def main():
                                "speedup_vs_plain_f64": round(pl32 / ms32, 3)}
             lb.close()
             log(f"32^4 eps={eps}: {ms32:.3f} ms (plain {pl32:.3f} ms)")
-        del big32
+
+    paper = None
+    if not args.no_extra and not args.no_paper:
+        paper = paper_table(torch, W, ctx, big, big32[0.3], eta32)
+        paper["eps"] = 0.3
+        log(f"paper table: {paper}")
+    del big32
 
     serving = None
     if not args.no_extra and not args.no_serve:
@@ -534,6 +610,7 @@ def main():
         "literal_8x8x8x8": literal,
         "multi_rhs_12": multi,
         "solve_32x4_f16": c3,
+        "paper_table1_32x4": paper,
         "dapply_32x4": dapply,
         "serving": serving,
         "roofline": roof_dom,
