@@ -235,6 +235,8 @@ def paper_table(torch, W, ctx, dims, U, eta, kappa=0.126, csw=1.0, tol=1e-14, n_
                 ms, st = run(W.SolverParams.make(ras=ras, **base))
                 grid[f"{nr}x{nd}"] = {"ms": round(ms, 3), "dv_count": st["dslash_full"],
                                       "converged": bool(st["converged"])}
+            log(f"scan NRAS={nr}: " + ", ".join(f"{k}: {v['ms']:.0f} ms" for k, v in grid.items()
+                                                 if k.startswith(f"{nr}x")))
         best = min((k for k in grid if grid[k]["converged"]), key=lambda k: grid[k]["ms"])
         out["scan_d0"] = {"best": best, "grid": grid}
     lat.close()
