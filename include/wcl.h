@@ -65,8 +65,9 @@ extern "C" {
 
 /* ---- RAS domain solver kernels ---- */
 #define WCL_BLOCK_AUTO 0
-#define WCL_BLOCK_FUSED 1   /* one workgroup per (domain, rhs), LDS-resident (extended volume <= 1024) */
-#define WCL_BLOCK_SPLIT 2   /* several workgroups per domain, one launch per MR step (any shape) */
+#define WCL_BLOCK_FUSED 1   /* one workgroup per (domain, rhs), on chip (extended volume <= 256) */
+#define WCL_BLOCK_SPLIT 2   /* several workgroups per domain, two launches per MR step (any shape) */
+/* WCL_BLOCK_AUTO takes the fused kernel when the extended domain fits it. */
 
 typedef struct wcl_ctx wcl_ctx;
 typedef struct wcl_lattice wcl_lattice;
@@ -107,8 +108,10 @@ typedef struct wcl_solver_params {
     wcl_ras_params ras;
 } wcl_solver_params;
 
-/* Per-solve statistics.  ms_* are HIP-event times of the categories of the
- * paper's timing chart (Sec. 4/5) as they exist on one device. */
+/* Per-solve statistics.  The counters follow the paper's timing chart
+ * (Sec. 4/5): dslash_full is its "Dv operation count", dslash_block and
+ * ras_sweeps measure the domain inversion work; ms_total is the HIP-event
+ * time of the whole solve on its stream. */
 typedef struct wcl_solve_stats {
     int outer_iters;
     int inner_iters;        /* summed over all inner solves */
