@@ -278,17 +278,17 @@ def serve_bench(W, I, np, ctx, n_req, slots):
     for k, d in enumerate(SERVE_SIZES):
         gauges[k] = I.random_gauge(d, 0.5, 1)
     log("serving: gauge fields generated")
-    pool = ThreadPoolExecutor(12)
-
-    def source(i):
-        return I.gaussian_source(SERVE_SIZES[kind[i]], 1000 + int(i))
+    # every source is drawn before the timed runs (12 host threads), so the
+    # request loop only submits and polls
+    with ThreadPoolExecutor(12) as pool:
+        sources = list(pool.map(lambda i: I.gaussian_source(SERVE_SIZES[kind[i]], 1000 + int(i)), range(n_req)))
+    log("serving: sources generated")
 
     def run(budget, arrivals):
         srv = W.Server(ctx, max_slots=slots, hbm_budget=budget)
         for k, d in enumerate(SERVE_SIZES):
             srv.register_gauge(k, d, gauges[k])
-        ahead = 48
-        futs = {i: pool.submit(source, i) for i in range(min(n_req, ahead))}
+        free = {k: [] for k in range(len(SERVE_SIZES))}   # solution buffers returned by finished requests
         inflight, done = {}, []
         nxt, late = 0, 0
         t0 = time.monotonic()
@@ -299,18 +299,19 @@ def serve_bench(W, I, np, ctx, n_req, slots):
                     break
                 if arrivals is not None and time.monotonic() < t0 + arrivals[nxt]:
                     break
-                eta = futs.pop(nxt).result()
-                if nxt + ahead < n_req:
-                    futs[nxt + ahead] = pool.submit(source, nxt + ahead)
                 if arrivals is not None and time.monotonic() > t0 + arrivals[nxt] + 0.005:
                     late += 1
-                t = srv.submit(int(kind[nxt]), float(kappa[nxt]), float(csw[nxt]), eta)
+                k = int(kind[nxt])
+                phi = free[k].pop() if free[k] else np.empty_like(sources[nxt])
+                t = srv.submit(k, float(kappa[nxt]), float(csw[nxt]), sources[nxt], phi=phi)
                 inflight[t] = nxt
                 nxt += 1
             for t in list(inflight):
                 r = srv.poll(t)
                 if r is not None:
-                    done.append((inflight.pop(t), r[1]))
+                    i = inflight.pop(t)
+                    free[int(kind[i])].append(r[0])
+                    done.append((i, r[1]))
             time.sleep(0.0005)
         T = time.monotonic() - t0
         srv.close()
@@ -340,7 +341,6 @@ def serve_bench(W, I, np, ctx, n_req, slots):
     opened["rate_per_s"] = round(lam, 3)
     opened["hbm_budget_bytes"] = 24 << 30
     log(f"serving: Poisson p50 {opened['p50_ms']} ms p99 {opened['p99_ms']} ms")
-    pool.shutdown()
     return {"closed_loop": closed, "poisson": opened, "slots": slots,
             "mix": {"x".join(map(str, d)): wt for d, wt in zip(SERVE_SIZES, SERVE_WEIGHTS)}}
 

@@ -74,54 +74,6 @@ WCL_DEV void ws_store(f4v* base, int NE, int e, const float s[24]) {
     for (int q = 0; q < 6; ++q) base[(size_t)q * NE + e] = f4v{s[4 * q], s[4 * q + 1], s[4 * q + 2], s[4 * q + 3]};
 }
 
-template <int MU, int GP>
-WCL_DEV void blk_hops(const BlockArgs& a, const f4v* rho, int blk, const int lc[4], const int x[4], int gi,
-                      float mk, float acc[24]) {
-    float s[24], h[12], w[12], u[18];
-    // forward neighbour: (1 - gamma_mu) U_mu(x) rho(x + mu)
-    {
-        int ln[4] = {lc[0], lc[1], lc[2], lc[3]};
-        bool in = true;
-        ln[MU] += 1;
-        if (ln[MU] == a.B.e[MU]) {
-            if (a.B.e[MU] == a.g.L[MU]) ln[MU] = 0;
-            else in = false;
-        }
-        if (in) {
-            float ph = (x[MU] == a.g.L[MU] - 1) ? (float)a.g.bc[MU] : 1.f;
-            ws_load(rho, a.NE, blk * a.B.ev + local_index(a.B, ln), s);
-            spin_project<MU, true>(s, h);
-            GaugeIO<GP>::load(a.gauge, a.g.V, MU, gi, u);
-            su3_apply2<false>(u, h, w);
-            spin_accumulate<MU, true>(w, mk * ph, acc);
-        }
-    }
-    // backward neighbour: (1 + gamma_mu) U_mu(x - mu)^dag rho(x - mu)
-    {
-        int ln[4] = {lc[0], lc[1], lc[2], lc[3]};
-        bool in = true;
-        ln[MU] -= 1;
-        if (ln[MU] < 0) {
-            if (a.B.e[MU] == a.g.L[MU]) ln[MU] = a.B.e[MU] - 1;
-            else in = false;
-        }
-        if (in) {
-            float ph = (x[MU] == 0) ? (float)a.g.bc[MU] : 1.f;
-            int y[4] = {x[0], x[1], x[2], x[3]};
-            y[MU] = x[MU] == 0 ? a.g.L[MU] - 1 : x[MU] - 1;
-            ws_load(rho, a.NE, blk * a.B.ev + local_index(a.B, ln), s);
-            spin_project<MU, false>(s, h);
-            GaugeIO<GP>::load(a.gauge, a.g.V, MU, geom_index(a.g, y), u);
-            su3_apply2<true>(u, h, w);
-            spin_accumulate<MU, false>(w, mk * ph, acc);
-        }
-    }
-}
-
-#ifndef WCL_BLK_PIPE
-#define WCL_BLK_PIPE 1
-#endif
-
 // Workspace index of the neighbour of extended site lc in direction mu
 // (forward or backward), or -1 when the hop leaves Omega' (Dirichlet).
 WCL_DEV int blk_neighbour(const Geom& g, const Blocks& B, const int lc[4], int mu, bool fwd) {
@@ -172,7 +124,6 @@ __global__ __launch_bounds__(256) void k_blk_dslash(BlockArgs a) {
         const f4v* rho = (const f4v*)a.rho + rhs * a.ws_stride;
         float acc[24];
         const float mk = (float)(-a.kappa);
-#if WCL_BLK_PIPE
         // the eight hops (x+, x-, y+, y-, z+, z-, t+, t-), software-pipelined:
         // hop k+1's neighbour and link are requested before hop k is computed
         int ni[8], li[8];
@@ -217,19 +168,6 @@ __global__ __launch_bounds__(256) void k_blk_dslash(BlockArgs a) {
                 for (int j = 0; j < 12; ++j) acc[12 * b + j] += r0[12 * b + j] + ck * y[j];
             }
         }
-#else
-        float r0[24];
-        ws_load(rho, a.NE, e, r0);
-        {
-            float c[72];
-            CloverIO<GP>::load(a.clover, a.g.V, gi, c);
-            clover_term(c, r0, (float)(a.csw * a.kappa), acc);
-        }
-        blk_hops<0, GP>(a, rho, blk, lc, x, gi, mk, acc);
-        blk_hops<1, GP>(a, rho, blk, lc, x, gi, mk, acc);
-        blk_hops<2, GP>(a, rho, blk, lc, x, gi, mk, acc);
-        blk_hops<3, GP>(a, rho, blk, lc, x, gi, mk, acc);
-#endif
         ws_store((f4v*)a.q + rhs * a.ws_stride, a.NE, e, acc);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {

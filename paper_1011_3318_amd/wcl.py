@@ -288,9 +288,14 @@ class Server:
         check(lib.wcl_register_gauge(self.h, config_id, (C.c_int * 4)(*dims), U.ctypes.data_as(C.POINTER(C.c_double))))
         self.dims[config_id] = tuple(dims)
 
-    def submit(self, config_id: int, kappa: float, csw: float, eta, params: SolverParams | None = None) -> int:
+    def submit(self, config_id: int, kappa: float, csw: float, eta, params: SolverParams | None = None,
+               phi=None) -> int:
+        """Queues a solve; phi (optional, complex128 like eta) receives the solution."""
         eta = np.ascontiguousarray(eta, dtype=np.complex128)
-        phi = np.zeros_like(eta)
+        if phi is None:
+            phi = np.zeros_like(eta)
+        elif phi.shape != eta.shape or phi.dtype != np.complex128 or not phi.flags.c_contiguous:
+            raise ValueError("phi must be a C-contiguous complex128 array shaped like eta")
         p = C.pointer(params) if params is not None else None
         req = Request(config_id, kappa, csw, p, eta.ctypes.data_as(C.POINTER(C.c_double)),
                       phi.ctypes.data_as(C.POINTER(C.c_double)))
