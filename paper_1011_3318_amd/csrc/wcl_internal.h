@@ -38,9 +38,9 @@ void wcl_set_error(const char* fmt, ...);
 // A site's internal index is
 //     col * Vc + t * S + (lx + cx*(ly + cy*lz)),   S = cx*cy*cz, Vc = S*Lt,
 // with col = Cx + nCx*(Cy + nCy*Cz) the column of (x,y,z).  A wavefront
-// streams along x inside one t-slice of one column, and consecutive
-// workgroups walk a column in t, so the +-t neighbours of a slice are read
-// while the previous slice is still in the XCD's L2.
+// streams along x inside one t-slice of one column and consecutive
+// workgroups walk a column in t, so neighbouring slices are read close
+// together in time (by workgroups of the same XCD, see xcd_remap).
 struct Geom {
     int L[4];
     int c[3];
