@@ -21,6 +21,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -88,10 +89,16 @@ MR_FLOPS = 96 + 48 + 96 + 96
 
 
 def source_hash(files) -> str:
+    """Hash of the kernel sources with comments and blank lines removed, so
+    that a comment edit does not invalidate the stored counter runs."""
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(ROOT, "paper_1011_3318_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1011_3318_amd", "csrc", f)) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for ln in text.splitlines():
+            ln = re.sub(r"//.*", "", ln).strip()
+            if ln:
+                h.update(ln.encode() + b"\n")
     return h.hexdigest()[:16]
 
 
