@@ -486,6 +486,34 @@ def main():
     plain_ms = (time.perf_counter() - t0) / args.steps * 1e3
     log(f"plain FP64 {plain_ms:.3f} ms")
 
+    # ---- the 4^4 plain-method anchor (eps 0.5, kappa 0.12): launch-bound FP64 BiCGStab
+    small = None
+    if not args.no_extra:
+        d4 = (4, 4, 4, 4)
+        l4 = W.Lattice(ctx, d4)
+        U4 = I.random_gauge(d4, 0.5, 1)
+        l4.upload_gauge(U4)
+        eta4 = I.gaussian_source(d4, 2)
+        e4, p4 = l4.pack(eta4, W.F64), l4.zeros(W.F64)
+        l4.solve_bicgstab_f64(1e-10, 1000, 0.12, 1.0, e4, p4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            _, st4 = l4.solve_bicgstab_f64(1e-10, 1000, 0.12, 1.0, e4, p4)
+        torch.cuda.synchronize()
+        ms4 = (time.perf_counter() - t0) / 20 * 1e3
+        small = {"lattice": list(d4), "kappa": 0.12, "ms": round(ms4, 3), "iters": st4["outer_iters"],
+                 "true_resid": st4["true_resid"], "us_per_iter": round(ms4 * 1e3 / st4["outer_iters"], 1)}
+        if not args.no_cpu_baseline:
+            from oracle import Oracle
+            o4 = Oracle(d4, U4)
+            t0 = time.perf_counter()
+            _, inf4 = o4.bicgstab(eta4, 0.12, 1.0, tol=1e-10)
+            small["oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+            small["oracle_iters"] = inf4["iters"]
+        l4.close()
+        log(f"4^4 plain FP64: {small}")
+
     # ---- 12 spin-colour point sources batched in one solve (same lattice)
     multi = None
     if not args.no_extra:
@@ -617,6 +645,7 @@ def main():
         "plain_f64_iters": pst["outer_iters"],
         "speedup_vs_plain_f64": round(plain_ms / ms_per_step, 3),
         "literal_8x8x8x8": literal,
+        "plain_4x4_f64": small,
         "multi_rhs_12": multi,
         "solve_32x4_f16": c3,
         "paper_table1_32x4": paper,
