@@ -147,4 +147,23 @@ def test_input_validation(W, ctx):
     assert e.value.code == W.EUNITARITY
     with pytest.raises(W.WclError):
         W.Lattice(ctx, (4, 4, 1, 4))
+    # largest volume: V * 144 reals must stay addressable with 32-bit indices
+    with pytest.raises(W.WclError) as e:
+        W.Lattice(ctx, (64, 64, 64, 64))
+    assert e.value.code == W.EINVAL
+    lat.upload_gauge(I.random_gauge(dims, 0.5, 1))
+    with pytest.raises(W.WclError) as e:
+        lat.apply_D(1, 0.1, 1.0, x, lat.empty(1), nrhs=0)
+    assert e.value.code == W.EINVAL
+    with pytest.raises(W.WclError) as e:
+        lat.apply_D(1, 0.1, 1.0, x, x)            # in and out alias
+    assert e.value.code == W.EINVAL
     lat.close()
+    # an HBM budget too small for the resident fields
+    small = W.Context(0, hbm_budget=1 << 20)
+    lat2 = W.Lattice(small, (8, 8, 8, 8))
+    with pytest.raises(W.WclError) as e:
+        lat2.upload_gauge(I.random_gauge((8, 8, 8, 8), 0.5, 1))
+    assert e.value.code == W.ENOMEM
+    lat2.close()
+    small.close()
