@@ -131,6 +131,188 @@ __global__ __launch_bounds__(256, WCL_DSLASH_MINWAVES) void k_dslash(DslashArgs 
     }
 }
 
+// ------------------------------------- x/y neighbours from the workgroup
+// With whole x rows in a wavefront (c_x = L_x lanes, c_x | 64) and 256 / c_x
+// consecutive y rows of one (z, t, column) slice per workgroup, the x and y
+// hops need no neighbour loads.  Each lane projects its own spinor twice per
+// direction: P- psi(s) is what s - mu needs for its forward hop, and
+// U_mu(s)^dag P+ psi(s) (built with the link the lane loads anyway for its
+// own forward hop) is what s + mu needs for its backward hop.  x hops pick
+// these up with a cross-lane permute inside the wavefront, y hops through
+// LDS; only the first and last rows of a workgroup load their y neighbour
+// from memory, unless the workgroup spans the whole y extent and wraps.
+// z and t hops keep the pipelined neighbour loads of k_dslash.
+bool dslash_xy_layout(const Geom& g) {
+    const int cx = g.c[0];
+    if (cx != g.L[0] || cx < 2 || 64 % cx != 0) return false;
+    return g.c[1] % (256 / cx) == 0;
+}
+
+// Keeps the scheduler from hoisting the next phase's loads above this point
+// (which would hold them in registers through the current phase).
+#define WCL_PHASE() __builtin_amdgcn_sched_barrier(0)
+
+// Forces v to be computed here: arithmetic is otherwise free to sink below
+// a barrier, holding its loaded operands in registers across it.
+template <typename T, int N>
+WCL_DEV void pin_values(T (&v)[N]) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) asm volatile("" : "+v"(v[k]));
+}
+
+// v as held by lane `src` of this wavefront
+WCL_DEV float lane_fetch(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+WCL_DEV double lane_fetch(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(src << 2, (int)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int GP, int SPI, int SPO, int EPI, int SPY, bool NT>
+#ifndef WCL_XY_MINWAVES
+#define WCL_XY_MINWAVES 1
+#endif
+__global__ __launch_bounds__(256, WCL_XY_MINWAVES) void k_dslash_xy(DslashArgs a) {
+    using T = typename Real<GP>::T;
+    static_assert((GP == WCL_F64) == (SPI == WCL_F64), "FP64 arithmetic needs FP64 spinors and links");
+    __shared__ T hf_y[12][256];   // P- psi(s): forward y hop of the row below
+    __shared__ T hb_y[12][256];   // U_y(s)^dag P+ psi(s): backward y hop of the row above
+    const Geom& g = a.g;
+    const int V = g.V;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int rhs = lb % a.nrhs;
+    if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
+    const int t = threadIdx.x;
+    const int i = (lb / a.nrhs) * 256 + t;   // V % 256 == 0: every lane has a site
+    const char* in = (const char*)a.in + rhs * a.in_stride;
+    const int R = g.c[0], NR = 256 / R;      // lanes per x row, rows per workgroup
+    const int r = t >> g.lc[0];
+    int x[4], nbr[8], lnk[8];
+    T ph[8];
+    geom_coords(g, i, x);
+    hop_sites(g, i, x, nbr, lnk, ph);
+    const T mk = T(-a.kappa);
+
+    T psi[24], uy[18];
+    SpinorIO<SPI>::load(in, V, i, psi);
+    GaugeIO<GP>::template load<NT>(a.gauge, V, 1, i, uy);
+    {
+        T h[12], w[12];
+        spin_project<1, true>(psi, h);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) hf_y[k][t] = h[k];
+        spin_project<1, false>(psi, h);
+        su3_apply2<true>(uy, h, w);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) hb_y[k][t] = w[k];
+    }
+    WCL_PHASE();
+
+    // x hops through the wavefront
+    T wf[12], wb[12];
+    {
+        T ux[18], h[12], hr[12];
+        GaugeIO<GP>::template load<NT>(a.gauge, V, 0, i, ux);
+        const int lane = t & 63, row0 = lane & ~(R - 1);
+        const int up = row0 | ((lane + 1) & (R - 1)), dn = row0 | ((lane + R - 1) & (R - 1));
+        spin_project<0, true>(psi, h);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) hr[k] = lane_fetch(h[k], up);
+        su3_apply2<false>(ux, hr, wf);
+        spin_project<0, false>(psi, h);
+        su3_apply2<true>(ux, h, hr);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) wb[k] = lane_fetch(hr[k], dn);
+    }
+    WCL_PHASE();
+
+    T acc[24];
+    {
+        const T ck = T(a.csw * a.kappa);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            T c[36], y[12];
+            CloverBlk<GP>::template load<NT>(a.clover, V, i, b, c);
+            herm6_apply(c, psi + 12 * b, y);
+#pragma unroll
+            for (int j = 0; j < 12; ++j) acc[12 * b + j] = psi[12 * b + j] + ck * y[j];
+            WCL_PHASE();
+        }
+    }
+    spin_accumulate<0, true>(wf, mk * ph[0], acc);
+    spin_accumulate<0, false>(wb, mk * ph[1], acc);
+    pin_values(acc);   // finish the site term and x hops before the barrier
+
+    // y hops from LDS; the edge rows of a workgroup that does not span y load
+    __syncthreads();
+    const bool wrap = NR == g.L[1];
+    {
+        T h[12], w[12];
+        if (r + 1 < NR || wrap) {
+            const int src = r + 1 < NR ? t + R : t - (NR - 1) * R;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) h[k] = hf_y[k][src];
+        } else {
+            T s[24];
+            SpinorIO<SPI>::load(in, V, nbr[2], s);
+            spin_project<1, true>(s, h);
+        }
+        su3_apply2<false>(uy, h, w);
+        spin_accumulate<1, true>(w, mk * ph[2], acc);
+    }
+    {
+        T w[12];
+        if (r > 0 || wrap) {
+            const int src = r > 0 ? t - R : t + (NR - 1) * R;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) w[k] = hb_y[k][src];
+        } else {
+            T s[24], u[18], h[12];
+            SpinorIO<SPI>::load(in, V, nbr[3], s);
+            GaugeIO<GP>::template load<NT>(a.gauge, V, 1, lnk[3], u);
+            spin_project<1, false>(s, h);
+            su3_apply2<true>(u, h, w);
+        }
+        spin_accumulate<1, false>(w, mk * ph[3], acc);
+    }
+
+    WCL_PHASE();
+    // z and t hops: the pipelined neighbour loads of k_dslash
+    constexpr int D = WCL_PIPE_DEPTH;
+    T sb[D][24], ub[D][18];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        SpinorIO<SPI>::load(in, V, nbr[4 + k], sb[(4 + k) % D]);
+        GaugeIO<GP>::template load_raw<NT>(a.gauge, V, (4 + k) / 2, lnk[4 + k], ub[(4 + k) % D]);
+    }
+
+    hop_chain<4, D, NT, GP, SPI>(a, in, nbr, lnk, ph, mk, sb, ub, acc);
+
+    if (EPI == DS_AXPY) {
+        T y[24];
+        SpinorIO<SPY>::load((const char*)a.y + rhs * a.y_stride, V, i, y);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[k] = y[k] - acc[k];
+    }
+    SpinorIO<SPO>::store((char*)a.out + rhs * a.out_stride, V, i, acc);
+    if (EPI == DS_DOT) {
+        double d[3] = {0.0, 0.0, 0.0};
+        T v[24];
+        SpinorIO<SPO>::load((const char*)a.a + rhs * a.a_stride, V, i, v);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            T ar = v[2 * k], ai = v[2 * k + 1], br = acc[2 * k], bi = acc[2 * k + 1];
+            d[0] += (double)(ar * br + ai * bi);
+            d[1] += (double)(ar * bi - ai * br);
+            d[2] += (double)(br * br + bi * bi);
+        }
+        block_reduce3(d, a.partial + 3 * (size_t)((lb / a.nrhs) + (size_t)rhs * (gridDim.x / a.nrhs)));
+    }
+}
+
 // ------------------------------------------------ several lanes per site
 // Stores the float groups of s that belong to `lane` of LPS lanes.
 template <int P>
@@ -276,6 +458,15 @@ __global__ __launch_bounds__(256) void k_dslash_ml(DslashArgs a) {
     }
 }
 
+// WCL_DSLASH_XY=0 keeps every launch on the neighbour-load kernel (A/B runs)
+static bool dslash_xy_enabled() {
+    static const bool on = [] {
+        const char* e = getenv("WCL_DSLASH_XY");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
 static size_t dslash_launch_bytes(int V, int gp, int spi, int spo) {
     return gauge_bytes(gp, V) + clover_bytes(gp, V) + spinor_rhs_bytes(spi, V) + spinor_rhs_bytes(spo, V);
 }
@@ -286,14 +477,28 @@ static int launch_t(const DslashArgs& a, hipStream_t st) {
     switch (a.lps) {
         case 2: k_dslash_ml<GP, SPI, SPO, EPI, SPY, 2><<<tiles * a.nrhs, 256, 0, st>>>(a); break;
         case 4: k_dslash_ml<GP, SPI, SPO, EPI, SPY, 4><<<tiles * a.nrhs, 256, 0, st>>>(a); break;
-        default:
+        default: {
             // non-temporal field loads only for one rhs streaming more than the
             // 256 MB Infinity Cache holds
-            if (a.nrhs == 1 && dslash_launch_bytes(a.g.V, GP, SPI, SPO) > (256u << 20))
+            const bool nt = a.nrhs == 1 && dslash_launch_bytes(a.g.V, GP, SPI, SPO) > (256u << 20);
+            // FP64 stays on the neighbour-load kernel: the exchange variant
+            // needs 448 VGPRs in double precision (one wave per SIMD)
+            bool xy = false;
+            if constexpr (GP != WCL_F64) {
+                if (dslash_xy_enabled() && dslash_xy_layout(a.g)) {
+                    xy = true;
+                    if (nt) k_dslash_xy<GP, SPI, SPO, EPI, SPY, true><<<tiles * a.nrhs, 256, 0, st>>>(a);
+                    else k_dslash_xy<GP, SPI, SPO, EPI, SPY, false><<<tiles * a.nrhs, 256, 0, st>>>(a);
+                }
+            }
+            if (xy) {
+            } else if (nt) {
                 k_dslash<GP, SPI, SPO, EPI, SPY, true><<<tiles * a.nrhs, 256, 0, st>>>(a);
-            else
+            } else {
                 k_dslash<GP, SPI, SPO, EPI, SPY, false><<<tiles * a.nrhs, 256, 0, st>>>(a);
+            }
             break;
+        }
     }
     WCL_HIP(hipGetLastError());
     return WCL_OK;

@@ -79,6 +79,72 @@ def test_apply_D_parity(W, ctx, prec, dims, bc):
     lat.close()
 
 
+def column_caps(L):
+    """Column cross-section the library picks: the largest power of two
+    dividing L_mu, at most 32 x 32 x 8."""
+    out = []
+    for l, cap in zip(L[:3], (32, 32, 8)):
+        c = 1
+        while c * 2 <= cap and l % (c * 2) == 0:
+            c *= 2
+        out.append(c)
+    return out
+
+
+def exchange_layout(L):
+    """True where the D-apply takes x and y neighbours from the workgroup
+    (whole x rows in a wavefront, 256 / c_x whole y rows per workgroup)."""
+    cx, cy, _ = column_caps(L)
+    return cx == L[0] and 64 % cx == 0 and cy % (256 // cx) == 0
+
+
+# lattices on the in-workgroup exchange path: y wrapping inside the workgroup
+# (16x16, 32x8, 8x32) and y rows leaving it (32x32, 16x32, 32x64: two columns)
+XY_CASES = [((16, 16, 4, 4), (1, 1, 1, -1)), ((32, 8, 2, 2), (-1, -1, 1, 1)), ((8, 32, 2, 4), (1, -1, -1, 1)),
+            ((32, 32, 2, 2), (-1, -1, 1, -1)), ((16, 32, 4, 2), (1, -1, 1, 1)), ((32, 64, 2, 2), (1, -1, 1, -1))]
+
+
+def test_exchange_cases_take_the_exchange_path():
+    assert all(exchange_layout(d) for d, _ in XY_CASES)
+    assert not any(exchange_layout(d) for d in [(4, 4, 4, 4), (6, 4, 10, 4), (8, 8, 8, 16), (24, 24, 24, 48)])
+    assert exchange_layout((32, 32, 32, 32)) and exchange_layout((16, 16, 16, 32))
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("dims,bc", XY_CASES)
+def test_apply_D_exchange_layouts(W, ctx, prec, dims, bc):
+    U, lat = make(W, ctx, dims, bc=bc)
+    kappa, csw = 0.126, 1.2
+    psi = I.gaussian_source(dims, 4)
+    x = lat.pack(psi, prec)
+    y = lat.empty(prec)
+    lat.apply_D(prec, kappa, csw, x, y)
+    got = lat.unpack(y, prec)
+    ref = Oracle(dims, U, bc=bc).apply_D(psi, kappa, csw)
+    assert rel_err(got, ref) <= TOL[prec]
+    # every site, not just the norm: a wrong neighbour shows up locally
+    site_err = np.linalg.norm((got - ref).reshape(len(ref), -1), axis=1)
+    assert site_err.max() <= 10 * TOL[prec] * np.linalg.norm(ref.reshape(len(ref), -1), axis=1).max()
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_apply_D_exchange_multi_rhs_equals_single(W, ctx, prec):
+    dims = (16, 16, 4, 4)
+    U, lat = make(W, ctx, dims, bc=(-1, 1, 1, -1))
+    psi = I.gaussian_source(dims, 6, nrhs=3)
+    x = lat.pack(psi, prec, nrhs=3)
+    y = lat.empty(prec, 3)
+    lat.apply_D(prec, 0.12, 1.0, x, y, nrhs=3)
+    many = lat.unpack(y, prec, nrhs=3)
+    for r in range(3):
+        xs = lat.pack(psi[r], prec)
+        ys = lat.empty(prec)
+        lat.apply_D(prec, 0.12, 1.0, xs, ys)
+        assert np.array_equal(lat.unpack(ys, prec), many[r])
+    lat.close()
+
+
 @pytest.mark.parametrize("prec", [1, 2])
 def test_apply_D_multi_rhs_equals_single(W, ctx, prec):
     dims = (8, 4, 4, 8)
