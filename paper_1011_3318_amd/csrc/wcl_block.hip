@@ -448,16 +448,25 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
             WCL_HOPS(0) WCL_HOPS(1) WCL_HOPS(2) WCL_HOPS(3)
 #undef WCL_HOPS
         }
+        // <q, rho> and <q, q>: FP32 over the site's 12 components, FP64
+        // across the workgroup
         double d[3] = {0.0, 0.0, 0.0};
         if (active) {
+            float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 const float qr = q[2 * k], qi = q[2 * k + 1];
                 const float rr = s_rho[(2 * k) * NT + l], ri = s_rho[(2 * k + 1) * NT + l];
-                d[0] += (double)(qr * rr + qi * ri);
-                d[1] += (double)(qr * ri - qi * rr);
-                d[2] += (double)(qr * qr + qi * qi);
+                f0 = fmad(qr, rr, f0);
+                f0 = fmad(qi, ri, f0);
+                f1 = fmad(qr, ri, f1);
+                f1 = fmad(-qi, rr, f1);
+                f2 = fmad(qr, qr, f2);
+                f2 = fmad(qi, qi, f2);
             }
+            d[0] = f0;
+            d[1] = f1;
+            d[2] = f2;
         }
         // every thread has finished reading its neighbours' rho and backward
         // terms after this barrier; the next reads of them follow the next
@@ -468,10 +477,12 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             const float pr = s_rho[(2 * k) * NT + l], pi = s_rho[(2 * k + 1) * NT + l];
-            xs[2 * k] += ar * pr - ai * pi;
-            xs[2 * k + 1] += ar * pi + ai * pr;
-            s_rho[(2 * k) * NT + l] = pr - (ar * q[2 * k] - ai * q[2 * k + 1]);
-            s_rho[(2 * k + 1) * NT + l] = pi - (ar * q[2 * k + 1] + ai * q[2 * k]);
+            xs[2 * k] = fmad(ar, pr, xs[2 * k]);
+            xs[2 * k] = fmad(-ai, pi, xs[2 * k]);
+            xs[2 * k + 1] = fmad(ar, pi, xs[2 * k + 1]);
+            xs[2 * k + 1] = fmad(ai, pr, xs[2 * k + 1]);
+            s_rho[(2 * k) * NT + l] = fmad(ai, q[2 * k + 1], fmad(-ar, q[2 * k], pr));
+            s_rho[(2 * k + 1) * NT + l] = fmad(-ai, q[2 * k], fmad(-ar, q[2 * k + 1], pi));
         }
     }
     // restriction to the owned sites and sum into the output

@@ -13,6 +13,12 @@ typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 
 #define WCL_DEV __device__ __forceinline__
 
+// a * b + c with one rounding.  The stencil arithmetic is written as chains
+// of these into the accumulators: a sum of products such as
+// acc += a*b - c*d would otherwise cost a multiply, an FMA and an add.
+WCL_DEV float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+WCL_DEV double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <int P>
 struct Real {
     using T = float;
@@ -154,8 +160,14 @@ WCL_DEV void reconstruct_row2(T u[18]) {
     for (int c = 0; c < 3; ++c) {
         const int a = (c + 1) % 3, b = (c + 2) % 3;
         // (row0_a row1_b - row0_b row1_a)^*
-        T re = RE(0, a) * RE(1, b) - IM(0, a) * IM(1, b) - (RE(0, b) * RE(1, a) - IM(0, b) * IM(1, a));
-        T im = RE(0, a) * IM(1, b) + IM(0, a) * RE(1, b) - (RE(0, b) * IM(1, a) + IM(0, b) * RE(1, a));
+        T re = RE(0, a) * RE(1, b);
+        re = fmad(-IM(0, a), IM(1, b), re);
+        re = fmad(-RE(0, b), RE(1, a), re);
+        re = fmad(IM(0, b), IM(1, a), re);
+        T im = RE(0, a) * IM(1, b);
+        im = fmad(IM(0, a), RE(1, b), im);
+        im = fmad(-RE(0, b), IM(1, a), im);
+        im = fmad(-IM(0, b), RE(1, a), im);
         RE(2, c) = re;
         IM(2, c) = -im;
     }
@@ -355,10 +367,14 @@ WCL_DEV void herm6_apply(const T* c, const T* x, T* y) {
         for (int b = a + 1; b < 6; ++b, ++k) {
             T re = c[6 + 2 * k], im = c[6 + 2 * k + 1];
             // y_a += c_ab x_b ; y_b += conj(c_ab) x_a
-            y[2 * a] += re * x[2 * b] - im * x[2 * b + 1];
-            y[2 * a + 1] += re * x[2 * b + 1] + im * x[2 * b];
-            y[2 * b] += re * x[2 * a] + im * x[2 * a + 1];
-            y[2 * b + 1] += re * x[2 * a + 1] - im * x[2 * a];
+            y[2 * a] = fmad(re, x[2 * b], y[2 * a]);
+            y[2 * a] = fmad(-im, x[2 * b + 1], y[2 * a]);
+            y[2 * a + 1] = fmad(re, x[2 * b + 1], y[2 * a + 1]);
+            y[2 * a + 1] = fmad(im, x[2 * b], y[2 * a + 1]);
+            y[2 * b] = fmad(re, x[2 * a], y[2 * b]);
+            y[2 * b] = fmad(im, x[2 * a + 1], y[2 * b]);
+            y[2 * b + 1] = fmad(re, x[2 * a + 1], y[2 * b + 1]);
+            y[2 * b + 1] = fmad(-im, x[2 * a], y[2 * b + 1]);
         }
 }
 
@@ -451,8 +467,10 @@ WCL_DEV void su3_apply2(const T u[18], const T h[12], T w[12]) {
                 const int ab = DAG ? 2 * (3 * b + a) : 2 * (3 * a + b);
                 const T ur = u[ab], ui = DAG ? -u[ab + 1] : u[ab + 1];
                 const T hr = h[6 * sp + 2 * b], hi = h[6 * sp + 2 * b + 1];
-                re += ur * hr - ui * hi;
-                im += ur * hi + ui * hr;
+                re = fmad(ur, hr, re);
+                re = fmad(-ui, hi, re);
+                im = fmad(ur, hi, im);
+                im = fmad(ui, hr, im);
             }
             w[6 * sp + 2 * a] = re;
             w[6 * sp + 2 * a + 1] = im;
@@ -467,7 +485,7 @@ WCL_DEV void clover_term(const T c[72], const T s[24], T ck, T acc[24]) {
     for (int k = 0; k < 2; ++k) {
         herm6_apply(c + 36 * k, s + 12 * k, y);
 #pragma unroll
-        for (int j = 0; j < 12; ++j) acc[12 * k + j] = s[12 * k + j] + ck * y[j];
+        for (int j = 0; j < 12; ++j) acc[12 * k + j] = fmad(ck, y[j], s[12 * k + j]);
     }
 }
 
