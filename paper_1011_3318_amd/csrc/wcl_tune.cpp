@@ -171,7 +171,7 @@ extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, dou
     // stage 3: inner tolerance, lanes per site of the D-apply
     {
         const Cand base3 = bestc;
-        for (double tol : {1e-2, 1e-3, 1e-4})
+        for (double tol : {1e-2, 1e-3, 1e-4, 1e-5})
             for (int lps : {1, 2}) {
                 Cand c = base3;
                 c.p.tol_inner = tol;
