@@ -554,7 +554,7 @@ def main():
         tb = measured_traffic("dapply_counters.json", DAPPLY_SOURCES, "1", V)
         roof = {"bound": "hbm", "achieved": f32["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": f32["frac"], "traffic": tb,
-                "kernel": "k_dslash<F32> full-lattice D-apply, 32^4, 672 algorithmic B/site x 1048576 sites "
+                "kernel": "k_dslash_xy<F32> full-lattice D-apply, 32^4, 672 algorithmic B/site x 1048576 sites "
                           "per launch", "us_per_launch": f32["us"]}
         lb.close()
         log(f"D-apply 32^4: {dapply}")
