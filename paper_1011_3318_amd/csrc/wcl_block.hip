@@ -354,7 +354,7 @@ struct SiteFields {
 #ifndef WCL_FUSED_MINWAVES
 #define WCL_FUSED_MINWAVES 2
 #endif
-template <int GP, int SRC, int VP, int NT>
+template <int GP, int SRC, int VP, int NT, bool RES>
 __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs a, int write_vj) {
     extern __shared__ float lds[];
     float* s_rho = lds;                 // [24][NT]
@@ -405,6 +405,40 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
         phb[mu] = (x[mu] == 0) ? (float)a.g.bc[mu] : 1.f;
     }
     const float ck = (float)(a.csw * a.kappa), mk = (float)(-a.kappa);
+    if constexpr (RES) {
+        // The residual update of the previous sweep (Algorithm 1), fused:
+        // r_j = r_{j-1} - D v_{j-1} at this site, with the own links and
+        // clover from the registers and the neighbours' v_{j-1} and backward
+        // links from memory (every site of Omega' sees the whole lattice).
+        if (active) {
+            const char* vp = (const char*)a.vprev + rhs * a.vprev_stride;
+            int nbr[8], lnk[8];
+            float ph[8];
+            hop_sites(a.g, gi, x, nbr, lnk, ph);
+            float acc[24];
+            {
+                float vv[24];
+                SpinorIO<VP>::load(vp, a.g.V, gi, vv);
+                F.site_term(vv, ck, acc);
+            }
+#define WCL_RHOP(K)                                                                   \
+    {                                                                                 \
+        float s[24], h[12], w[12], u[18];                                             \
+        SpinorIO<VP>::load(vp, a.g.V, nbr[K], s);                                     \
+        if ((K) % 2 == 0) F.template link<(K) / 2>(u);                                \
+        else GaugeIO<GP>::template load<false>(a.gauge, a.g.V, (K) / 2, lnk[K], u);   \
+        spin_project<(K) / 2, (K) % 2 == 0>(s, h);                                    \
+        su3_apply2<(K) % 2 != 0>(u, h, w);                                            \
+        spin_accumulate<(K) / 2, (K) % 2 == 0>(w, mk * ph[K], acc);                   \
+    }
+            WCL_RHOP(0) WCL_RHOP(1) WCL_RHOP(2) WCL_RHOP(3) WCL_RHOP(4) WCL_RHOP(5) WCL_RHOP(6) WCL_RHOP(7)
+#undef WCL_RHOP
+#pragma unroll
+            for (int k = 0; k < 24; ++k) rho[k] -= acc[k];
+            if (a.rout && block_owned(a.B, lc))
+                SpinorIO<VP>::store((char*)a.rout + rhs * a.rout_stride, a.g.V, gi, rho);
+        }
+    }
     // rho lives in LDS between steps: only its owner thread writes it
 #pragma unroll
     for (int k = 0; k < 24; ++k) s_rho[k * NT + l] = rho[k];
@@ -502,22 +536,24 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
 
 int fused_threads(int ev) { return ev <= 256 ? 256 : (ev <= 512 ? 512 : 0); }
 
-template <int GP, int SRC, int VP, int NT>
+template <int GP, int SRC, int VP, int NT, bool RES>
 static int launch_fused_t(const BlockArgs& a, hipStream_t st) {
     const size_t lds = (size_t)72 * NT * sizeof(float);
     // dynamic LDS above the 64 KB default; set once per instantiation (thread-safe static)
-    static const hipError_t attr = hipFuncSetAttribute((const void*)k_blk_fused<GP, SRC, VP, NT>,
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_blk_fused<GP, SRC, VP, NT, RES>,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     WCL_HIP(attr);
-    k_blk_fused<GP, SRC, VP, NT><<<a.B.nblocks * a.nrhs, NT, lds, st>>>(a, a.vj != nullptr);
+    k_blk_fused<GP, SRC, VP, NT, RES><<<a.B.nblocks * a.nrhs, NT, lds, st>>>(a, a.vj != nullptr);
     WCL_HIP(hipGetLastError());
     return WCL_OK;
 }
 
 int launch_blk_fused(const BlockArgs& a, int gp, int src_prec, hipStream_t st) {
     const int nt = fused_threads(a.B.ev);
-#define WCL_F(G, S, NT) \
-    if (gp == G && src_prec == S && nt == NT) return launch_fused_t<G, S, G, NT>(a, st)
+    const bool res = a.vprev != nullptr;
+#define WCL_F(G, S, NT)                                                                    \
+    if (gp == G && src_prec == S && nt == NT)                                              \
+        return res ? launch_fused_t<G, S, G, NT, true>(a, st) : launch_fused_t<G, S, G, NT, false>(a, st)
     WCL_F(WCL_F32, WCL_F32, 256);
     WCL_F(WCL_F32, WCL_F32, 512);
     WCL_F(WCL_F16, WCL_F32, 256);

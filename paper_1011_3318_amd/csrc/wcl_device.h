@@ -501,6 +501,26 @@ WCL_DEV void hop_compute(const T s[24], T u[18], T f, T acc[24]) {
     spin_accumulate<MU, FWD>(w, f, acc);
 }
 
+// The eight hops in the order (x+, x-, y+, y-, z+, z-, t+, t-): neighbour
+// site, link site and boundary phase of each.
+template <typename T>
+WCL_DEV void hop_sites(const Geom& g, int i, const int x[4], int nbr[8], int lnk[8], T ph[8]) {
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        const bool wf = x[mu] + 1 == g.L[mu];
+        y[mu] = wf ? 0 : x[mu] + 1;
+        nbr[2 * mu] = geom_index(g, y);
+        lnk[2 * mu] = i;
+        ph[2 * mu] = wf ? T(g.bc[mu]) : T(1);
+        const bool wb = x[mu] == 0;
+        y[mu] = wb ? g.L[mu] - 1 : x[mu] - 1;
+        nbr[2 * mu + 1] = geom_index(g, y);
+        lnk[2 * mu + 1] = nbr[2 * mu + 1];
+        ph[2 * mu + 1] = wb ? T(g.bc[mu]) : T(1);
+    }
+}
+
 // ------------------------------------------------------ XCD remapping ---
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that
 // each XCD walks a contiguous range of logical workgroup ids (and thereby a

@@ -76,6 +76,13 @@ struct BlockArgs {
     void* vj;            // optional copy of this sweep's correction (storage precision)
     size_t vj_stride;
     int accumulate;      // out += x instead of out = x
+    // fused residual update (on-chip path, sweeps after the first): the
+    // projection source is r_j = src - D vprev, formed in the kernel; r_j is
+    // written to rout at the owned sites when rout != nullptr
+    const void* vprev;   // v_{j-1}, storage precision
+    size_t vprev_stride;
+    void* rout;          // r_j, storage precision
+    size_t rout_stride;
     double kappa, csw;
     int nrhs;
     double* partial;     // [rhs][nblocks][wpb][3]

@@ -105,7 +105,7 @@ size_t nested_workspace_bytes(const wcl_lattice* lat, const wcl_solver_params* p
     if (prm && prm->precond == WCL_PRECOND_RAS) {
         Blocks B;
         if (make_blocks(lat, &prm->ras, &B) == WCL_OK) {
-            b += 3 * spinor_rhs_bytes(prm->ras.storage, lat->V) * nrhs;   // v_j, r_j ping-pong
+            b += 4 * spinor_rhs_bytes(prm->ras.storage, lat->V) * nrhs;   // v_j, r_j ping-pong
             if (fused_threads(B.ev) != 256) b += (size_t)3 * 96 * B.nblocks * B.ev * nrhs;   // split workspaces
         }
     }
@@ -212,25 +212,43 @@ static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int stora
     if (!fused) WCL_CHECK(ws->get("ras.q", wsb, &a.q));
     if (!fused) WCL_CHECK(ws->get("ras.x", wsb, &a.x));
     if (!fused) WCL_CHECK(ws->get("ras.partial", (size_t)24 * nrhs * B.nblocks * wpb, (void**)&a.partial));
-    void *vj = nullptr, *rbuf[2] = {nullptr, nullptr};
+    // Between sweeps r_{j+1} = r_j - D v_j.  The on-chip path forms it inside
+    // the next sweep's kernel (v_j ping-pongs, since that kernel reads the
+    // neighbours' v_j while writing its own v_{j+1}); the split path runs a
+    // full-lattice D-apply with the axpy epilogue.
+    void *vj[2] = {nullptr, nullptr}, *rbuf[2] = {nullptr, nullptr};
     if (B.n_ras > 1) {
-        WCL_CHECK(ws->get("ras.vj", sst * nrhs, &vj));
+        WCL_CHECK(ws->get("ras.vj", sst * nrhs, &vj[0]));
+        if (fused && B.n_ras > 2) WCL_CHECK(ws->get("ras.vj1", sst * nrhs, &vj[1]));
         WCL_CHECK(ws->get("ras.r0", sst * nrhs, &rbuf[0]));
         if (B.n_ras > 2) WCL_CHECK(ws->get("ras.r1", sst * nrhs, &rbuf[1]));
     }
     for (int j = 0; j < B.n_ras; ++j) {
         const bool last = j == B.n_ras - 1;
+        a.accumulate = j > 0;
+        a.vj_stride = sst;
+        // projection r_{Omega'} = P r, then N_dominv MR steps, then R + sum
+        if (fused) {
+            // sweep j reads r_{j-1} (r itself for j = 1) and v_{j-1}
+            const void* src = j <= 1 ? r : rbuf[(j - 1) % 2];
+            const int src_prec = j <= 1 ? WCL_F32 : storage;
+            a.src = src;
+            a.src_stride = j <= 1 ? s32 : sst;
+            a.vprev = j == 0 ? nullptr : vj[(j - 1) % 2];
+            a.vprev_stride = sst;
+            a.rout = (j == 0 || last) ? nullptr : rbuf[j % 2];
+            a.rout_stride = sst;
+            a.vj = last ? nullptr : vj[j % 2];
+            WCL_CHECK(launch_blk_fused(a, storage, src_prec, st));
+            if (j > 0 && stats) stats->dslash_full += nrhs;
+            continue;
+        }
         const void* src = j == 0 ? r : rbuf[(j - 1) % 2];
         const int src_prec = j == 0 ? WCL_F32 : storage;
         a.src = src;
         a.src_stride = j == 0 ? s32 : sst;
-        a.accumulate = j > 0;
-        a.vj = last ? nullptr : vj;
-        a.vj_stride = sst;
-        // projection r_{Omega'} = P r, then N_dominv MR steps, then R + sum
-        if (fused) {
-            WCL_CHECK(launch_blk_fused(a, storage, src_prec, st));
-        } else {
+        a.vj = last ? nullptr : vj[0];
+        {
             WCL_CHECK(launch_blk_project(a, src_prec, st));
             for (int k = 0; k < B.n_dominv; ++k) {
                 WCL_CHECK(launch_blk_dslash(a, storage, st));
@@ -243,7 +261,7 @@ static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int stora
             d.g = lat->g;
             d.gauge = lat->gauge[storage];
             d.clover = lat->clover[storage];
-            d.in = vj;
+            d.in = vj[0];
             d.in_stride = sst;
             d.y = src;
             d.y_stride = a.src_stride;
