@@ -157,6 +157,33 @@ __global__ __launch_bounds__(256) void k_dot(BlasGrid bg, const Scal* sc, const 
     block_reduce3(d, partial + 3 * ((size_t)rhs * bg.G + wg));
 }
 
+// BiCGStab start in one pass: x = p = v = 0, r = rhat = b; partials of
+// <b, b> and |b|^2 for the active rhs (the same sums k_dot forms)
+template <int P>
+__global__ __launch_bounds__(256) void k_init(BlasGrid bg, const Scal* sc, const void* b_, void* x_, void* r_,
+                                               void* rh_, void* p_, void* v_, double* partial) {
+    using E = typename Vec<P>::E;
+    BLAS_PROLOGUE
+    double d[3] = {0, 0, 0};
+    const bool act = sc[rhs].active;
+    const E* b = (const E*)b_ + base;
+    E* x = (E*)x_ + base;
+    E* r = (E*)r_ + base;
+    E* rh = (E*)rh_ + base;
+    E* p = (E*)p_ + base;
+    E* v = (E*)v_ + base;
+    BLAS_FOR(k) {
+        const E bv = b[k];
+        x[k] = E{};
+        p[k] = E{};
+        v[k] = E{};
+        r[k] = bv;
+        rh[k] = bv;
+        if (act) dot_acc(bv, bv, d);
+    }
+    block_reduce3(d, partial + 3 * ((size_t)rhs * bg.G + wg));
+}
+
 // y = a (copy), or y = 0 when a == nullptr (a fill kernel, not a memset)
 template <int P>
 __global__ __launch_bounds__(256) void k_copy(BlasGrid bg, const void* a_, void* y_) {
@@ -210,7 +237,7 @@ __global__ __launch_bounds__(256) void k_to_f64_scaled(int V, int G, const Scal*
 // ----------------------------------------------------------- finalize ---
 // One workgroup per rhs adds the G partial triples in a fixed order and
 // applies the scalar step of BiCGStab selected by `kind`.
-__global__ __launch_bounds__(256) void k_finalize(const double* partial, int G, Scal* sc, int kind) {
+__global__ __launch_bounds__(256) void k_finalize(const double* partial, int G, Scal* sc, int kind, Scal* mirror) {
     const int rhs = blockIdx.x;
     Scal& S = sc[rhs];
     double d[3] = {0, 0, 0};
@@ -259,6 +286,12 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partial, int G, 
         case FIN_RR: S.rr = s2; break;
         case FIN_RR0: S.rr0 = s2; S.rr = s2; break;
     }
+    if (mirror) {
+        // the host's pinned copy: the solver loop reads it after a stream
+        // synchronisation, with no copy of its own
+        mirror[rhs] = S;
+        __threadfence_system();
+    }
 }
 
 // ------------------------------------------------------------ launchers --
@@ -306,6 +339,11 @@ int blas_dot(int prec, int64_t V, int nrhs, const Scal* sc, const void* a, const
     DISPATCH_P(prec, k_dot, sc, a, b, partial);
     return WCL_OK;
 }
+int blas_init(int prec, int64_t V, int nrhs, const Scal* sc, const void* b, void* x, void* r, void* rh, void* p,
+              void* v, double* partial, hipStream_t st) {
+    DISPATCH_P(prec, k_init, sc, b, x, r, rh, p, v, partial);
+    return WCL_OK;
+}
 int blas_copy(int prec, int64_t V, int nrhs, const void* a, void* y, hipStream_t st) {
     DISPATCH_P(prec, k_copy, a, y);
     return WCL_OK;
@@ -324,8 +362,8 @@ int blas_to_f64_scaled(int64_t V, int nrhs, const Scal* sc, const void* a32, voi
     WCL_HIP(hipGetLastError());
     return WCL_OK;
 }
-int blas_finalize(const double* partial, int G, int nrhs, Scal* sc, int kind, hipStream_t st) {
-    k_finalize<<<nrhs, 256, 0, st>>>(partial, G, sc, kind);
+int blas_finalize(const double* partial, int G, int nrhs, Scal* sc, int kind, hipStream_t st, Scal* mirror) {
+    k_finalize<<<nrhs, 256, 0, st>>>(partial, G, sc, kind, mirror);
     WCL_HIP(hipGetLastError());
     return WCL_OK;
 }

@@ -53,9 +53,15 @@ int blas_xr_update(int prec, int64_t V, int nrhs, const Scal* sc, void* x, const
 int blas_dot(int prec, int64_t V, int nrhs, const Scal* sc, const void* a, const void* b, double* partial,
              hipStream_t st);
 int blas_copy(int prec, int64_t V, int nrhs, const void* a, void* y, hipStream_t st);
+// x = p = v = 0, r = rhat = b, partials of <b, b> for the active rhs
+int blas_init(int prec, int64_t V, int nrhs, const Scal* sc, const void* b, void* x, void* r, void* rh, void* p,
+              void* v, double* partial, hipStream_t st);
 int blas_to_f32_scaled(int64_t V, int nrhs, const Scal* sc, const void* a64, void* y32, hipStream_t st);
 int blas_to_f64_scaled(int64_t V, int nrhs, const Scal* sc, const void* a32, void* y64, hipStream_t st);
-int blas_finalize(const double* partial, int G, int nrhs, Scal* sc, int kind, hipStream_t st);
+// mirror (optional): device-visible pinned host array that also receives the
+// updated scalars of the active rhs
+int blas_finalize(const double* partial, int G, int nrhs, Scal* sc, int kind, hipStream_t st,
+                  Scal* mirror = nullptr);
 
 // ------------------------------------------------------ domain solves ---
 struct BlockArgs {

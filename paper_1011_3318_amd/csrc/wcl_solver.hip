@@ -310,8 +310,9 @@ struct Engine {
     int Gb, Gd;
     void *r, *rh, *p, *v, *s, *t, *ph, *sh;
     double* partial;
-    Scal* d;   // device scalars [nrhs]
-    Scal* h;   // pinned host mirror
+    Scal* d;      // device scalars [nrhs]
+    Scal* h;      // pinned host mirror
+    Scal* hmap;   // h as the device addresses it (written by the finalize kernels)
 
     int init(const Precond* K) {
         V = lat->V;
@@ -371,8 +372,9 @@ struct Engine {
         if (stats) stats->dslash_full += nrhs;
         return launch_dslash(a, gp, P, P, DS_AXPY, P, st);
     }
+    // The finalize kernel before every pull has written the active rhs'
+    // scalars into h already; inactive rhs do not change on the device.
     int pull() {
-        WCL_HIP(hipMemcpyAsync(h, d, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st));
         WCL_HIP(hipStreamSynchronize(st));
         return WCL_OK;
     }
@@ -388,11 +390,7 @@ struct Engine {
             int max_restarts, EngineResult* res) {
         WCL_CHECK(init(K));
         WCL_CHECK(ws->host_scal(tag, nrhs, &h));
-        WCL_CHECK(blas_copy(P, V, nrhs, nullptr, x, st));
-        WCL_CHECK(blas_copy(P, V, nrhs, b, r, st));
-        WCL_CHECK(blas_copy(P, V, nrhs, b, rh, st));
-        WCL_CHECK(blas_copy(P, V, nrhs, nullptr, p, st));
-        WCL_CHECK(blas_copy(P, V, nrhs, nullptr, v, st));
+        WCL_HIP(hipHostGetDevicePointer((void**)&hmap, h, 0));
         for (int i = 0; i < nrhs; ++i) {
             Scal z{};
             z.rho[0] = z.rho_old[0] = z.alpha[0] = z.omega[0] = 1.0;
@@ -400,8 +398,8 @@ struct Engine {
             h[i] = z;
         }
         WCL_CHECK(push());
-        WCL_CHECK(blas_dot(P, V, nrhs, d, rh, r, partial, st));
-        WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RHO, st));
+        WCL_CHECK(blas_init(P, V, nrhs, d, b, x, r, rh, p, v, partial, st));
+        WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RHO, st, hmap));
         WCL_CHECK(pull());
         std::vector<double> bnorm(nrhs, 0.0), rh2(nrhs, 0.0);
         std::vector<int> conv(nrhs, 0), restarts(nrhs, 0);
@@ -440,7 +438,7 @@ struct Engine {
             WCL_CHECK(apply_dot(sh, t, s));
             WCL_CHECK(blas_finalize(partial, Gd, nrhs, d, FIN_OMEGA, st));
             WCL_CHECK(blas_xr_update(P, V, nrhs, d, x, ph, sh, s, t, r, rh, partial, st));
-            WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RHO, st));
+            WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RHO, st, hmap));
             WCL_CHECK(pull());
             bool changed = false, want_true = false;
             std::vector<int> restart(nrhs, 0);
@@ -474,7 +472,7 @@ struct Engine {
                 // true residual in the engine's precision: t = b - D x
                 WCL_CHECK(residual(b, x, t));
                 WCL_CHECK(blas_dot(P, V, nrhs, d, t, t, partial, st));
-                WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RR, st));
+                WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RR, st, hmap));
                 WCL_CHECK(pull());
                 for (int i = 0; i < nrhs; ++i) {
                     if (restart[i] != 3) continue;
@@ -524,7 +522,7 @@ struct Engine {
                 for (int i = 0; i < nrhs; ++i) h[i].breakdown = 0;
                 WCL_CHECK(push());
                 WCL_CHECK(blas_dot(P, V, nrhs, d, rh, r, partial, st));
-                WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RHO, st));
+                WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RHO, st, hmap));
                 WCL_CHECK(pull());
                 for (int i = 0; i < nrhs; ++i) {
                     if (restart[i] != 1 && restart[i] != 2) continue;
@@ -549,7 +547,7 @@ struct Engine {
             WCL_CHECK(push());
             WCL_CHECK(residual(b, x, t));
             WCL_CHECK(blas_dot(P, V, nrhs, d, t, t, partial, st));
-            WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RR, st));
+            WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RR, st, hmap));
             WCL_CHECK(pull());
             res->true_resid = 0.0;
             for (int i = 0; i < nrhs; ++i)
@@ -736,13 +734,13 @@ int wcl_solve_bicgstab_f64(wcl_lattice* lat, double tol, int max_iter, double ka
         rc = eng.push();
         if (rc == WCL_OK) rc = eng.residual(eta_dev, phi_dev, eng.t);
         if (rc == WCL_OK) rc = blas_dot(WCL_F64, lat->V, 1, eng.d, eng.t, eng.t, eng.partial, st);
-        if (rc == WCL_OK) rc = blas_finalize(eng.partial, eng.Gb, 1, eng.d, FIN_RR, st);
+        if (rc == WCL_OK) rc = blas_finalize(eng.partial, eng.Gb, 1, eng.d, FIN_RR, st, eng.hmap);
         if (rc == WCL_OK) rc = eng.pull();
         if (rc == WCL_OK) {
             // |eta|: reuse the dot on the right-hand side
             double rr = eng.h[0].rr;
             rc = blas_dot(WCL_F64, lat->V, 1, eng.d, eta_dev, eta_dev, eng.partial, st);
-            if (rc == WCL_OK) rc = blas_finalize(eng.partial, eng.Gb, 1, eng.d, FIN_RR, st);
+            if (rc == WCL_OK) rc = blas_finalize(eng.partial, eng.Gb, 1, eng.d, FIN_RR, st, eng.hmap);
             if (rc == WCL_OK) rc = eng.pull();
             if (rc == WCL_OK) S->true_resid = eng.h[0].rr > 0 ? std::sqrt(rr / eng.h[0].rr) : 0.0;
         }
