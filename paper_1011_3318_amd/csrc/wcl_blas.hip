@@ -72,14 +72,13 @@ struct BlasGrid {
     for (int k = wg * 256 + threadIdx.x; k < bg.n; k += step)          \
         if (k < bg.last || (k & 63) < bg.rem)
 
-// p = r + beta (p - omega v), beta = (rho/rho_old)(alpha/omega); partial |p|^2
+// p = r + beta (p - omega v), beta = (rho/rho_old)(alpha/omega)
 template <int P>
 __global__ __launch_bounds__(256) void k_p_update(BlasGrid bg, const Scal* sc, const void* r_, void* p_,
-                                                   const void* v_, double* partial) {
+                                                   const void* v_) {
     using E = typename Vec<P>::E;
     BLAS_PROLOGUE
     const Scal& S = sc[rhs];
-    double d[3] = {0, 0, 0};
     if (S.active) {
         double t1r, t1i, t2r, t2i, br, bi;
         cdiv(S.rho[0], S.rho[1], S.rho_old[0], S.rho_old[1], t1r, t1i);
@@ -91,12 +90,9 @@ __global__ __launch_bounds__(256) void k_p_update(BlasGrid bg, const Scal* sc, c
         const E* v = (const E*)v_ + base;
         BLAS_FOR(k) {
             E pv = p[k] - cm(wr, wi, v[k]);
-            E np = r[k] + cm(br, bi, pv);
-            p[k] = np;
-            dot_acc(np, np, d);
+            p[k] = r[k] + cm(br, bi, pv);
         }
     }
-    block_reduce3(d, partial + 3 * ((size_t)rhs * bg.G + wg));
 }
 
 // s = r - alpha v
@@ -320,8 +316,8 @@ int blas_partials(int prec, int64_t V) { return blas_grid(prec, V).G; }
     } while (0)
 
 int blas_p_update(int prec, int64_t V, int nrhs, const Scal* sc, const void* r, void* p, const void* v,
-                  double* partial, hipStream_t st) {
-    DISPATCH_P(prec, k_p_update, sc, r, p, v, partial);
+                  hipStream_t st) {
+    DISPATCH_P(prec, k_p_update, sc, r, p, v);
     return WCL_OK;
 }
 int blas_s_update(int prec, int64_t V, int nrhs, const Scal* sc, const void* r, const void* v, void* s,

@@ -45,7 +45,7 @@ enum { FIN_ALPHA = 0, FIN_OMEGA = 1, FIN_RHO = 2, FIN_PP = 3, FIN_RR = 4, FIN_RR
 
 int blas_partials(int prec, int64_t V);
 int blas_p_update(int prec, int64_t V, int nrhs, const Scal* sc, const void* r, void* p, const void* v,
-                  double* partial, hipStream_t st);
+                  hipStream_t st);
 int blas_s_update(int prec, int64_t V, int nrhs, const Scal* sc, const void* r, const void* v, void* s,
                   hipStream_t st);
 int blas_xr_update(int prec, int64_t V, int nrhs, const Scal* sc, void* x, const void* ph, const void* sh,

@@ -403,6 +403,9 @@ struct Engine {
         WCL_CHECK(pull());
         std::vector<double> bnorm(nrhs, 0.0), rh2(nrhs, 0.0);
         std::vector<int> conv(nrhs, 0), restarts(nrhs, 0);
+        // |b - D x| / |b| of the rhs whose convergence a true residual
+        // confirmed (x does not change afterwards); -1 = not known
+        std::vector<double> tres(nrhs, -1.0);
         for (int i = 0; i < nrhs; ++i) {
             if (!act[i]) continue;
             if (!std::isfinite(h[i].rr)) {
@@ -427,7 +430,7 @@ struct Engine {
         };
         while (any_active() && it < max_iter) {
             ++it;
-            WCL_CHECK(blas_p_update(P, V, nrhs, d, r, p, v, partial, st));
+            WCL_CHECK(blas_p_update(P, V, nrhs, d, r, p, v, st));
             std::vector<int> a_now(nrhs);
             for (int i = 0; i < nrhs; ++i) a_now[i] = h[i].active;
             if (K) WCL_CHECK((*K)(p, ph, d, a_now));
@@ -480,6 +483,7 @@ struct Engine {
                     if (trel <= tol) {
                         h[i].active = 0;
                         conv[i] = 1;
+                        tres[i] = trel;
                         restart[i] = 0;
                         changed = true;
                     } else if (restarts[i] < max_restarts) {
@@ -542,16 +546,25 @@ struct Engine {
             act[i] = conv[i];
         }
         if (true_check) {
-            // report |b - D x| / |b| for every rhs
-            for (int i = 0; i < nrhs; ++i) h[i].active = bnorm[i] > 0 ? 1 : 0;
-            WCL_CHECK(push());
-            WCL_CHECK(residual(b, x, t));
-            WCL_CHECK(blas_dot(P, V, nrhs, d, t, t, partial, st));
-            WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RR, st, hmap));
-            WCL_CHECK(pull());
+            // report |b - D x| / |b| for every rhs: computed again only for
+            // the rhs that no true-residual check confirmed
+            bool any = false;
+            for (int i = 0; i < nrhs; ++i) {
+                h[i].active = (bnorm[i] > 0 && tres[i] < 0) ? 1 : 0;
+                any = any || h[i].active;
+            }
+            if (any) {
+                WCL_CHECK(push());
+                WCL_CHECK(residual(b, x, t));
+                WCL_CHECK(blas_dot(P, V, nrhs, d, t, t, partial, st));
+                WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RR, st, hmap));
+                WCL_CHECK(pull());
+                for (int i = 0; i < nrhs; ++i)
+                    if (h[i].active) tres[i] = std::sqrt(h[i].rr) / bnorm[i];
+            }
             res->true_resid = 0.0;
             for (int i = 0; i < nrhs; ++i)
-                if (bnorm[i] > 0) res->true_resid = std::max(res->true_resid, std::sqrt(h[i].rr) / bnorm[i]);
+                if (bnorm[i] > 0) res->true_resid = std::max(res->true_resid, tres[i]);
         }
         return WCL_OK;
     }
