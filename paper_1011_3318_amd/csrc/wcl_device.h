@@ -521,6 +521,26 @@ WCL_DEV void hop_sites(const Geom& g, int i, const int x[4], int nbr[8], int lnk
     }
 }
 
+// <a, b> (complex) and |b|^2 over one site's 12 components, added to d: FMA
+// chains in the arithmetic precision, then one conversion to FP64 each.
+template <typename T>
+WCL_DEV void site_dot3(const T a[24], const T b[24], double d[3]) {
+    T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const T ar = a[2 * k], ai = a[2 * k + 1], br = b[2 * k], bi = b[2 * k + 1];
+        s0 = fmad(ar, br, s0);
+        s0 = fmad(ai, bi, s0);
+        s1 = fmad(ar, bi, s1);
+        s1 = fmad(-ai, br, s1);
+        s2 = fmad(br, br, s2);
+        s2 = fmad(bi, bi, s2);
+    }
+    d[0] += (double)s0;
+    d[1] += (double)s1;
+    d[2] += (double)s2;
+}
+
 // ------------------------------------------------------ XCD remapping ---
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that
 // each XCD walks a contiguous range of logical workgroup ids (and thereby a

@@ -99,13 +99,7 @@ __global__ __launch_bounds__(256, WCL_DSLASH_MINWAVES) void k_dslash(DslashArgs 
         if (active) {
             T v[24];
             SpinorIO<SPO>::load((const char*)a.a + rhs * a.a_stride, a.g.V, i, v);
-#pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                T ar = v[2 * k], ai = v[2 * k + 1], br = acc[2 * k], bi = acc[2 * k + 1];
-                d[0] += (double)(ar * br + ai * bi);
-                d[1] += (double)(ar * bi - ai * br);
-                d[2] += (double)(br * br + bi * bi);
-            }
+            site_dot3(v, acc, d);
         }
         block_reduce3(d, a.partial + 3 * (size_t)((lb / a.nrhs) + (size_t)rhs * (gridDim.x / a.nrhs)));
     }
@@ -282,13 +276,7 @@ __global__ __launch_bounds__(256, WCL_XY_MINWAVES) void k_dslash_xy(DslashArgs a
         double d[3] = {0.0, 0.0, 0.0};
         T v[24];
         SpinorIO<SPO>::load((const char*)a.a + rhs * a.a_stride, V, i, v);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            T ar = v[2 * k], ai = v[2 * k + 1], br = acc[2 * k], bi = acc[2 * k + 1];
-            d[0] += (double)(ar * br + ai * bi);
-            d[1] += (double)(ar * bi - ai * br);
-            d[2] += (double)(br * br + bi * bi);
-        }
+        site_dot3(v, acc, d);
         block_reduce3(d, a.partial + 3 * (size_t)((lb / a.nrhs) + (size_t)rhs * (gridDim.x / a.nrhs)));
     }
 }
@@ -426,13 +414,7 @@ __global__ __launch_bounds__(256) void k_dslash_ml(DslashArgs a) {
         if (active && lane == 0) {
             T v[24];
             SpinorIO<SPO>::load((const char*)a.a + rhs * a.a_stride, V, i, v);
-#pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                T ar = v[2 * k], ai = v[2 * k + 1], br = acc[2 * k], bi = acc[2 * k + 1];
-                d[0] += (double)(ar * br + ai * bi);
-                d[1] += (double)(ar * bi - ai * br);
-                d[2] += (double)(br * br + bi * bi);
-            }
+            site_dot3(v, acc, d);
         }
         block_reduce3(d, a.partial + 3 * (size_t)(tile + (size_t)rhs * (gridDim.x / a.nrhs)));
     }
