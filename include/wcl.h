@@ -213,7 +213,7 @@ int wcl_solve_bicgstab_f64(wcl_lattice* lat, double tol, int max_iter, double ka
  * storage precision, inner tolerance and the D-apply's lanes per site, by
  * timing complete nested solves of eta on this lattice: stage 1 scans
  * domain shape {4^4, 4^3x8, 8^4} x overlap {0, 1} x storage {FP32, FP16};
- * stage 2 scans N_dominv {2, 4, 6} x NRAS {1, 2, 3}; stage 3 the inner
+ * stage 2 scans N_dominv {2, 3, 4, 5, 6} x NRAS {1, 2, 3, 4}; stage 3 the inner
  * tolerance {1e-2, 1e-3, 1e-4, 1e-5} and lanes per site {1, 2}.  Candidates that
  * do not converge are skipped.  With cache_path != NULL the result is read
  * from / appended to that JSON-lines file, keyed by device architecture,

@@ -160,8 +160,8 @@ extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, dou
     // stage 2: N_dominv x NRAS
     {
         const Cand base2 = bestc;
-        for (int nd : {2, 4, 6})
-            for (int nr : {1, 2, 3}) {
+        for (int nd : {2, 3, 4, 5, 6})
+            for (int nr : {1, 2, 3, 4}) {
                 Cand c = base2;
                 c.p.ras.n_dominv = nd;
                 c.p.ras.n_ras = nr;
