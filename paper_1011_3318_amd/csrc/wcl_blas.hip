@@ -180,20 +180,6 @@ __global__ __launch_bounds__(256) void k_init(BlasGrid bg, const Scal* sc, const
     block_reduce3(d, partial + 3 * ((size_t)rhs * bg.G + wg));
 }
 
-// y = a (copy), or y = 0 when a == nullptr (a fill kernel, not a memset)
-template <int P>
-__global__ __launch_bounds__(256) void k_copy(BlasGrid bg, const void* a_, void* y_) {
-    using E = typename Vec<P>::E;
-    BLAS_PROLOGUE
-    E* y = (E*)y_ + base;
-    if (a_) {
-        const E* a = (const E*)a_ + base;
-        BLAS_FOR(k) y[k] = a[k];
-    } else {
-        BLAS_FOR(k) y[k] = E{};
-    }
-}
-
 // FP64 -> FP32 with factor 1/sqrt(S.pp) (inner right-hand side b = p/|p|);
 // FP32 -> FP64 with factor sqrt(S.pp) (p^ = |p| y).  One thread per FP32
 // element: float4 g of site i holds FP64 components 2g and 2g+1.
@@ -338,10 +324,6 @@ int blas_dot(int prec, int64_t V, int nrhs, const Scal* sc, const void* a, const
 int blas_init(int prec, int64_t V, int nrhs, const Scal* sc, const void* b, void* x, void* r, void* rh, void* p,
               void* v, double* partial, hipStream_t st) {
     DISPATCH_P(prec, k_init, sc, b, x, r, rh, p, v, partial);
-    return WCL_OK;
-}
-int blas_copy(int prec, int64_t V, int nrhs, const void* a, void* y, hipStream_t st) {
-    DISPATCH_P(prec, k_copy, a, y);
     return WCL_OK;
 }
 int blas_to_f32_scaled(int64_t V, int nrhs, const Scal* sc, const void* a64, void* y32, hipStream_t st) {

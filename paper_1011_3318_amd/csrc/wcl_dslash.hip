@@ -145,10 +145,10 @@ WCL_DEV double lane_fetch(double v, int src) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-template <int GP, int SPI, int SPO, int EPI, int SPY, bool NT>
 #ifndef WCL_XY_MINWAVES
-#define WCL_XY_MINWAVES 1
+#define WCL_XY_MINWAVES 2
 #endif
+template <int GP, int SPI, int SPO, int EPI, int SPY, bool NT>
 __global__ __launch_bounds__(256, WCL_XY_MINWAVES) void k_dslash_xy(DslashArgs a) {
     using T = typename Real<GP>::T;
     static_assert((GP == WCL_F64) == (SPI == WCL_F64), "FP64 arithmetic needs FP64 spinors and links");
@@ -443,17 +443,9 @@ static int launch_t(const DslashArgs& a, hipStream_t st) {
             // non-temporal field loads only for one rhs streaming more than the
             // 256 MB Infinity Cache holds
             const bool nt = a.nrhs == 1 && dslash_launch_bytes(a.g.V, GP, SPI, SPO) > (256u << 20);
-            // FP64 stays on the neighbour-load kernel: the exchange variant
-            // needs 448 VGPRs in double precision (one wave per SIMD)
-            bool xy = false;
-            if constexpr (GP != WCL_F64) {
-                if (dslash_xy_enabled() && dslash_xy_layout(a.g)) {
-                    xy = true;
-                    if (nt) k_dslash_xy<GP, SPI, SPO, EPI, SPY, true><<<tiles * a.nrhs, 256, 0, st>>>(a);
-                    else k_dslash_xy<GP, SPI, SPO, EPI, SPY, false><<<tiles * a.nrhs, 256, 0, st>>>(a);
-                }
-            }
-            if (xy) {
+            if (dslash_xy_enabled() && dslash_xy_layout(a.g)) {
+                if (nt) k_dslash_xy<GP, SPI, SPO, EPI, SPY, true><<<tiles * a.nrhs, 256, 0, st>>>(a);
+                else k_dslash_xy<GP, SPI, SPO, EPI, SPY, false><<<tiles * a.nrhs, 256, 0, st>>>(a);
             } else if (nt) {
                 k_dslash<GP, SPI, SPO, EPI, SPY, true><<<tiles * a.nrhs, 256, 0, st>>>(a);
             } else {

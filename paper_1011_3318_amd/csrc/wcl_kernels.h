@@ -52,7 +52,6 @@ int blas_xr_update(int prec, int64_t V, int nrhs, const Scal* sc, void* x, const
                    const void* s, const void* t, void* r, const void* rh, double* partial, hipStream_t st);
 int blas_dot(int prec, int64_t V, int nrhs, const Scal* sc, const void* a, const void* b, double* partial,
              hipStream_t st);
-int blas_copy(int prec, int64_t V, int nrhs, const void* a, void* y, hipStream_t st);
 // x = p = v = 0, r = rhat = b, partials of <b, b> for the active rhs
 int blas_init(int prec, int64_t V, int nrhs, const Scal* sc, const void* b, void* x, void* r, void* rh, void* p,
               void* v, double* partial, hipStream_t st);
