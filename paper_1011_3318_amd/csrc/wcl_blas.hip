@@ -347,7 +347,8 @@ int blas_finalize(const double* partial, int G, int nrhs, Scal* sc, int kind, hi
 }
 
 // Restart of the rhs flagged with breakdown == 2: r = src (if given),
-// rhat = r, p = v = 0.
+// rhat = r, v = 0 and p = r (the p update's result after a restart, whose
+// scalars give beta (p - omega v) = 0).
 template <int P>
 __global__ __launch_bounds__(256) void k_restart(BlasGrid bg, const Scal* sc, const void* src_, void* r_, void* rh_,
                                                   void* p_, void* v_) {
@@ -363,7 +364,7 @@ __global__ __launch_bounds__(256) void k_restart(BlasGrid bg, const Scal* sc, co
         E rv = src ? src[k] : r[k];
         r[k] = rv;
         rh[k] = rv;
-        p[k] = E{};
+        p[k] = rv;
         v[k] = E{};
     }
 }

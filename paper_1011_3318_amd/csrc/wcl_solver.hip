@@ -313,6 +313,11 @@ struct Engine {
     Scal* d;      // device scalars [nrhs]
     Scal* h;      // pinned host mirror
     Scal* hmap;   // h as the device addresses it (written by the finalize kernels)
+    hipEvent_t ev = nullptr;   // recorded after each iteration's last finalize
+
+    ~Engine() {
+        if (ev) (void)hipEventDestroy(ev);
+    }
 
     int init(const Precond* K) {
         V = lat->V;
@@ -335,6 +340,7 @@ struct Engine {
         }
         WCL_CHECK(ws->get(name("partial"), (size_t)24 * nrhs * std::max(Gb, Gd), (void**)&partial));
         WCL_CHECK(ws->get(name("scal"), sizeof(Scal) * nrhs, (void**)&d));
+        if (!ev) WCL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         return WCL_OK;
     }
     int apply_dot(const void* in, void* out, const void* a) {
@@ -428,9 +434,16 @@ struct Engine {
                 if (h[i].active) return true;
             return false;
         };
+        // The next iteration's p update is enqueued before the host check of
+        // this one and the host waits on an event recorded before it, so the
+        // GPU computes p while the host decides.  That is safe: convergence
+        // leaves p unused, and a restart sets p = r itself (what the update
+        // gives after a restart), overwriting the speculative p.
+        bool p_ready = false;
         while (any_active() && it < max_iter) {
             ++it;
-            WCL_CHECK(blas_p_update(P, V, nrhs, d, r, p, v, st));
+            if (!p_ready) WCL_CHECK(blas_p_update(P, V, nrhs, d, r, p, v, st));
+            p_ready = false;
             std::vector<int> a_now(nrhs);
             for (int i = 0; i < nrhs; ++i) a_now[i] = h[i].active;
             if (K) WCL_CHECK((*K)(p, ph, d, a_now));
@@ -442,7 +455,12 @@ struct Engine {
             WCL_CHECK(blas_finalize(partial, Gd, nrhs, d, FIN_OMEGA, st));
             WCL_CHECK(blas_xr_update(P, V, nrhs, d, x, ph, sh, s, t, r, rh, partial, st));
             WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RHO, st, hmap));
-            WCL_CHECK(pull());
+            WCL_HIP(hipEventRecord(ev, st));
+            if (it < max_iter) {
+                WCL_CHECK(blas_p_update(P, V, nrhs, d, r, p, v, st));
+                p_ready = true;
+            }
+            WCL_HIP(hipEventSynchronize(ev));
             bool changed = false, want_true = false;
             std::vector<int> restart(nrhs, 0);
             for (int i = 0; i < nrhs; ++i) {
