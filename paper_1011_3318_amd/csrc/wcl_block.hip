@@ -354,7 +354,10 @@ struct SiteFields {
 #ifndef WCL_FUSED_MINWAVES
 #define WCL_FUSED_MINWAVES 2
 #endif
-template <int GP, int SRC, int VP, int NT, bool RES>
+// RES: 0 = no residual update (first sweep); 1 = r_j = src - D vprev from
+// all eight hops; 2 = r_j = src - (the hops of D vprev that leave the
+// domain), src being the previous sweep's final MR residual (no overlap).
+template <int GP, int SRC, int VP, int NT, int RES>
 __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs a, int write_vj) {
     extern __shared__ float lds[];
     float* s_rho = lds;                 // [24][NT]
@@ -405,7 +408,36 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
         phb[mu] = (x[mu] == 0) ? (float)a.g.bc[mu] : 1.f;
     }
     const float ck = (float)(a.csw * a.kappa), mk = (float)(-a.kappa);
-    if constexpr (RES) {
+    if constexpr (RES == 2) {
+        // Without overlap the MR iteration keeps rho = r_{j-1} - D_Omega x on
+        // the domain, and v_{j-1} = x there, so r_j = r_{j-1} - D v_{j-1} is
+        // the previous sweep's final rho minus the hops of D v_{j-1} that
+        // leave the domain (Dirichlet D_Omega drops exactly those).
+        if (active) {
+            const char* vp = (const char*)a.vprev + rhs * a.vprev_stride;
+            int nbr[8], lnk[8];
+            float ph[8];
+            hop_sites(a.g, gi, x, nbr, lnk, ph);
+            float acc[24];
+#pragma unroll
+            for (int k = 0; k < 24; ++k) acc[k] = 0.f;
+#define WCL_XHOP(K)                                                                       \
+    if (((K) % 2 == 0 ? nf[(K) / 2] : nb[(K) / 2]) < 0) {                                 \
+        float s[24], h[12], w[12], u[18];                                                 \
+        SpinorIO<VP>::load(vp, a.g.V, nbr[K], s);                                         \
+        if ((K) % 2 == 0) F.template link<(K) / 2>(u);                                    \
+        else GaugeIO<GP>::template load<false>(a.gauge, a.g.V, (K) / 2, lnk[K], u);       \
+        spin_project<(K) / 2, (K) % 2 == 0>(s, h);                                        \
+        su3_apply2<(K) % 2 != 0>(u, h, w);                                                \
+        spin_accumulate<(K) / 2, (K) % 2 == 0>(w, mk * ph[K], acc);                       \
+    }
+            WCL_XHOP(0) WCL_XHOP(1) WCL_XHOP(2) WCL_XHOP(3) WCL_XHOP(4) WCL_XHOP(5) WCL_XHOP(6) WCL_XHOP(7)
+#undef WCL_XHOP
+#pragma unroll
+            for (int k = 0; k < 24; ++k) rho[k] -= acc[k];
+        }
+    }
+    if constexpr (RES == 1) {
         // The residual update of the previous sweep (Algorithm 1), fused:
         // r_j = r_{j-1} - D v_{j-1} at this site, with the own links and
         // clover from the registers and the neighbours' v_{j-1} and backward
@@ -521,6 +553,15 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
     }
     // restriction to the owned sites and sum into the output
     if (!active || !block_owned(a.B, lc)) return;
+    if constexpr (RES != 1) {
+        if (a.rout) {
+            // this sweep's final MR residual, the next sweep's starting point
+            float rn[24];
+#pragma unroll
+            for (int k = 0; k < 24; ++k) rn[k] = s_rho[k * NT + l];
+            SpinorIO<VP>::store((char*)a.rout + rhs * a.rout_stride, a.g.V, gi, rn);
+        }
+    }
     char* out = (char*)a.out + rhs * a.out_stride;
     if (a.accumulate) {
         float o[24];
@@ -536,7 +577,7 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
 
 int fused_threads(int ev) { return ev <= 256 ? 256 : (ev <= 512 ? 512 : 0); }
 
-template <int GP, int SRC, int VP, int NT, bool RES>
+template <int GP, int SRC, int VP, int NT, int RES>
 static int launch_fused_t(const BlockArgs& a, hipStream_t st) {
     const size_t lds = (size_t)72 * NT * sizeof(float);
     // dynamic LDS above the 64 KB default; set once per instantiation (thread-safe static)
@@ -550,10 +591,12 @@ static int launch_fused_t(const BlockArgs& a, hipStream_t st) {
 
 int launch_blk_fused(const BlockArgs& a, int gp, int src_prec, hipStream_t st) {
     const int nt = fused_threads(a.B.ev);
-    const bool res = a.vprev != nullptr;
+    const int res = a.vprev == nullptr ? 0 : (a.res_boundary ? 2 : 1);
 #define WCL_F(G, S, NT)                                                                    \
     if (gp == G && src_prec == S && nt == NT)                                              \
-        return res ? launch_fused_t<G, S, G, NT, true>(a, st) : launch_fused_t<G, S, G, NT, false>(a, st)
+        return res == 0   ? launch_fused_t<G, S, G, NT, 0>(a, st)                          \
+               : res == 1 ? launch_fused_t<G, S, G, NT, 1>(a, st)                          \
+                          : launch_fused_t<G, S, G, NT, 2>(a, st)
     WCL_F(WCL_F32, WCL_F32, 256);
     WCL_F(WCL_F32, WCL_F32, 512);
     WCL_F(WCL_F16, WCL_F32, 256);

@@ -81,13 +81,18 @@ struct BlockArgs {
     void* vj;            // optional copy of this sweep's correction (storage precision)
     size_t vj_stride;
     int accumulate;      // out += x instead of out = x
-    // fused residual update (on-chip path, sweeps after the first): the
-    // projection source is r_j = src - D vprev, formed in the kernel; r_j is
-    // written to rout at the owned sites when rout != nullptr
-    const void* vprev;   // v_{j-1}, storage precision
+    // fused residual update (on-chip path, sweeps after the first), with
+    // vprev = v_{j-1}:
+    //   res_boundary == 0: src = r_{j-1}; the kernel forms r_j = src - D vprev
+    //     and writes r_j to rout at the owned sites;
+    //   res_boundary == 1 (no overlap): src = the previous sweep's final MR
+    //     residual rho_N = r_{j-1} - D_Omega v_{j-1}; the kernel adds only the
+    //     hops that leave the domain, and writes its own final rho_N to rout.
+    const void* vprev;   // storage precision
     size_t vprev_stride;
-    void* rout;          // r_j, storage precision
+    void* rout;          // storage precision
     size_t rout_stride;
+    int res_boundary;
     double kappa, csw;
     int nrhs;
     double* partial;     // [rhs][nblocks][wpb][3]

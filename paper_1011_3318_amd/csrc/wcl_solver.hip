@@ -192,6 +192,7 @@ static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int stora
     const size_t s32 = spinor_rhs_bytes(WCL_F32, V), sst = spinor_rhs_bytes(storage, V);
     bool fused = false;
     WCL_CHECK(pick_kernel(B, kernel, &fused));
+    const int no_overlap = B.s[0] == 0 && B.s[1] == 0 && B.s[2] == 0 && B.s[3] == 0;
     const int NE = fused ? 0 : B.nblocks * B.ev, wpb = (B.ev + 255) / 256;
     BlockArgs a{};
     a.g = lat->g;
@@ -229,16 +230,26 @@ static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int stora
         a.vj_stride = sst;
         // projection r_{Omega'} = P r, then N_dominv MR steps, then R + sum
         if (fused) {
-            // sweep j reads r_{j-1} (r itself for j = 1) and v_{j-1}
-            const void* src = j <= 1 ? r : rbuf[(j - 1) % 2];
-            const int src_prec = j <= 1 ? WCL_F32 : storage;
-            a.src = src;
-            a.src_stride = j <= 1 ? s32 : sst;
             a.vprev = j == 0 ? nullptr : vj[(j - 1) % 2];
             a.vprev_stride = sst;
-            a.rout = (j == 0 || last) ? nullptr : rbuf[j % 2];
             a.rout_stride = sst;
             a.vj = last ? nullptr : vj[j % 2];
+            a.res_boundary = no_overlap;
+            int src_prec;
+            if (no_overlap) {
+                // sweep j > 0 starts from sweep j-1's final MR residual and
+                // adds the hops of D v_{j-1} that cross domain boundaries
+                a.src = j == 0 ? r : rbuf[(j - 1) % 2];
+                a.src_stride = j == 0 ? s32 : sst;
+                src_prec = j == 0 ? WCL_F32 : storage;
+                a.rout = last ? nullptr : rbuf[j % 2];
+            } else {
+                // sweep j reads r_{j-1} (r itself for j = 1), forms r_j
+                a.src = j <= 1 ? r : rbuf[(j - 1) % 2];
+                a.src_stride = j <= 1 ? s32 : sst;
+                src_prec = j <= 1 ? WCL_F32 : storage;
+                a.rout = (j == 0 || last) ? nullptr : rbuf[j % 2];
+            }
             WCL_CHECK(launch_blk_fused(a, storage, src_prec, st));
             if (j > 0 && stats) stats->dslash_full += nrhs;
             continue;
