@@ -554,10 +554,32 @@ WCL_DEV int xcd_remap(int b, int n) {
 }
 
 // --------------------------------------------------------- reductions ---
+// v of the lane selected by the DPP pattern CTRL (both 32-bit halves moved)
+template <int CTRL>
+WCL_DEV double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+WCL_DEV double lane_read(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes (all active), the same value in every lane: DPP
+// butterflies inside each row of 16 (quad_perm [1,0,3,2], quad_perm
+// [2,3,0,1], row_half_mirror, row_mirror; each pair adds the same two
+// values, so every lane of a row ends with the same bits), then the four
+// row sums read in a fixed order.  No LDS traffic and no bpermute latency.
 WCL_DEV double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
+    v += dpp_move<0x141>(v);
+    v += dpp_move<0x140>(v);
+    return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 
 // Sum of d[0..2] over the workgroup (up to 1024 threads) in a fixed order;
