@@ -518,11 +518,16 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
         // across the workgroup
         double d[3] = {0.0, 0.0, 0.0};
         if (active) {
+            // all 24 LDS reads issued before the arithmetic (one wait, not 12)
+            float rv[24];
+#pragma unroll
+            for (int k = 0; k < 24; ++k) rv[k] = s_rho[k * NT + l];
+            __builtin_amdgcn_sched_barrier(0);
             float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 const float qr = q[2 * k], qi = q[2 * k + 1];
-                const float rr = s_rho[(2 * k) * NT + l], ri = s_rho[(2 * k + 1) * NT + l];
+                const float rr = rv[2 * k], ri = rv[2 * k + 1];
                 f0 = fmad(qr, rr, f0);
                 f0 = fmad(qi, ri, f0);
                 f1 = fmad(qr, ri, f1);
@@ -540,9 +545,13 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
         wg_allreduce3<NT / 64>(d, s_red);
         const float ar = d[2] > 0 ? (float)(d[0] / d[2]) : 0.f;
         const float ai = d[2] > 0 ? (float)(d[1] / d[2]) : 0.f;
+        float pv[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) pv[k] = s_rho[k * NT + l];
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            const float pr = s_rho[(2 * k) * NT + l], pi = s_rho[(2 * k + 1) * NT + l];
+            const float pr = pv[2 * k], pi = pv[2 * k + 1];
             xs[2 * k] = fmad(ar, pr, xs[2 * k]);
             xs[2 * k] = fmad(-ai, pi, xs[2 * k]);
             xs[2 * k + 1] = fmad(ar, pi, xs[2 * k + 1]);
