@@ -221,17 +221,30 @@ __global__ __launch_bounds__(256) void k_to_f64_scaled(int V, int G, const Scal*
 // applies the scalar step of BiCGStab selected by `kind`.
 __global__ __launch_bounds__(256) void k_finalize(const double* partial, int G, Scal* sc, int kind, Scal* mirror) {
     const int rhs = blockIdx.x;
-    Scal& S = sc[rhs];
+    // thread 0 fetches the solver state now, so that its latency overlaps
+    // that of the partial sums
+    Scal S;
+    if (threadIdx.x == 0) S = sc[rhs];
+    // each thread sums its partials in ascending order, four loads in flight
     double d[3] = {0, 0, 0};
-    for (int k = threadIdx.x; k < G; k += 256) {
-        const double* q = partial + 3 * ((size_t)rhs * G + k);
-        d[0] += q[0];
-        d[1] += q[1];
-        d[2] += q[2];
+    const double* q = partial + 3 * (size_t)rhs * G;
+    int k = threadIdx.x;
+    for (; k + 3 * 256 < G; k += 4 * 256) {
+        double v[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[u][c] = q[3 * (k + 256 * u) + c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) d[c] += v[u][c];
     }
+    for (; k < G; k += 256)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) d[c] += q[3 * k + c];
     __shared__ double tot[3];
-    block_reduce3(d, tot);
-    __syncthreads();
+    block_reduce3(d, tot);   // thread 0 writes tot and is the only reader
     if (threadIdx.x != 0 || !S.active) return;
     const double s0 = tot[0], s1 = tot[1], s2 = tot[2];
     switch (kind) {
@@ -268,6 +281,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partial, int G, 
         case FIN_RR: S.rr = s2; break;
         case FIN_RR0: S.rr0 = s2; S.rr = s2; break;
     }
+    sc[rhs] = S;
     if (mirror) {
         // the host's pinned copy: the solver loop reads it after a stream
         // synchronisation, with no copy of its own

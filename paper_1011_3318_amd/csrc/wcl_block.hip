@@ -584,7 +584,7 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
     if (write_vj) SpinorIO<VP>::store((char*)a.vj + rhs * a.vj_stride, a.g.V, gi, xs);
 }
 
-int fused_threads(int ev) { return ev <= 256 ? 256 : (ev <= 512 ? 512 : 0); }
+int fused_threads(int ev) { return ev <= 256 ? 256 : 0; }
 
 template <int GP, int SRC, int VP, int NT, int RES>
 static int launch_fused_t(const BlockArgs& a, hipStream_t st) {
@@ -607,11 +607,8 @@ int launch_blk_fused(const BlockArgs& a, int gp, int src_prec, hipStream_t st) {
                : res == 1 ? launch_fused_t<G, S, G, NT, 1>(a, st)                          \
                           : launch_fused_t<G, S, G, NT, 2>(a, st)
     WCL_F(WCL_F32, WCL_F32, 256);
-    WCL_F(WCL_F32, WCL_F32, 512);
     WCL_F(WCL_F16, WCL_F32, 256);
-    WCL_F(WCL_F16, WCL_F32, 512);
     WCL_F(WCL_F16, WCL_F16, 256);
-    WCL_F(WCL_F16, WCL_F16, 512);
 #undef WCL_F
     wcl_set_error("fused domain solver: unsupported case (storage %d, source %d, extended volume %d)", gp, src_prec,
                   a.B.ev);
