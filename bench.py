@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--block", default="4x4x4x4", help="solve mode: domain shape")
     ap.add_argument("--overlap", type=int, default=0, help="solve mode: overlap s")
     ap.add_argument("--storage", default="f16", choices=["f32", "f16"], help="solve mode: RAS storage")
+    ap.add_argument("--dapply-prec", default="f32", choices=["f64", "f32", "f16"], help="dapply mode: precision")
     ap.add_argument("--n-ras", type=int, default=3)
     ap.add_argument("--n-dominv", type=int, default=4)
     ap.add_argument("--tol-inner", type=float, default=1e-4)
@@ -381,8 +382,10 @@ def main():
         big = (32, 32, 32, 32)
         lb = W.Lattice(ctx, big)
         lb.upload_gauge(I.random_gauge(big, 1.0, 1))
-        us = time_dapply(torch, I, lb, 1, n_warm=3, n_timed=10)
-        print(json.dumps({"mode": "dapply", "V": lb.V, "us": us, "launches": 13}))
+        prec = {"f64": 0, "f32": 1, "f16": 2}[args.dapply_prec]
+        us = time_dapply(torch, I, lb, prec, n_warm=3, n_timed=10)
+        print(json.dumps({"mode": "dapply", "prec": args.dapply_prec, "V": lb.V, "us": us,
+                          "GBps": DAPPLY_BYTES[prec] * lb.V / us / 1e3, "launches": 13}))
         lb.close()
         ctx.close()
         return
