@@ -1,8 +1,9 @@
 // Vector kernels of the BiCGStab solvers (FP64 outer, FP32 inner), batched
 // over right-hand sides.  The solver scalars live on the device (struct
 // Scal per rhs) so that no kernel waits for the host; every reduction writes
-// per-workgroup partial sums which a finalize kernel adds in a fixed order
-// (results are bitwise reproducible run to run).
+// per-workgroup partial sums, which a finalize kernel (or every workgroup of
+// the update kernel that needs the scalar) adds in a fixed order, so results
+// are bitwise reproducible run to run.
 #include "wcl_device.h"
 #include "wcl_kernels.h"
 
@@ -36,6 +37,56 @@ WCL_DEV f4v cm(double cr, double ci, f4v a) {
 }
 WCL_DEV d2v cm(double cr, double ci, d2v a) {
     return d2v{cr * a.x - ci * a.y, cr * a.y + ci * a.x};
+}
+
+// The G partial triples of one rhs added in a fixed order: thread t takes
+// partials t, t + 256, ... in ascending order (four loads in flight), then
+// the workgroup sum.  Every thread receives the totals, and every workgroup
+// that reduces the same partials obtains the same bits.
+WCL_DEV void partial_total(const double* partial, int G, int rhs, double t[3]) {
+    double d[3] = {0, 0, 0};
+    const double* q = partial + 3 * (size_t)rhs * G;
+    int k = threadIdx.x;
+    for (; k + 3 * 256 < G; k += 4 * 256) {
+        double v[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[u][c] = q[3 * (k + 256 * u) + c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) d[c] += v[u][c];
+    }
+    for (; k < G; k += 256)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) d[c] += q[3 * k + c];
+    __shared__ double tot[3];
+    block_reduce3(d, tot);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) t[c] = tot[c];
+}
+
+// alpha = rho / <rhat, v> from the totals (<rhat, v> in t[0], t[1]);
+// returns true on breakdown (<rhat, v> = 0, alpha set to 0)
+WCL_DEV bool alpha_step(const double rho[2], const double t[3], double& ar, double& ai) {
+    if (t[0] == 0.0 && t[1] == 0.0) {
+        ar = ai = 0.0;
+        return true;
+    }
+    cdiv(rho[0], rho[1], t[0], t[1], ar, ai);
+    return false;
+}
+
+// omega = <t, s> / <t, t> from the totals of the partials of <s, t>, |t|^2
+WCL_DEV void omega_step(const double t[3], double& wr, double& wi) {
+    if (t[2] > 0.0) {
+        wr = t[0] / t[2];
+        wi = -t[1] / t[2];
+    } else {
+        wr = wi = 0.0;
+    }
 }
 
 // <a, b> contributions (re, im) and |b|^2
@@ -95,32 +146,58 @@ __global__ __launch_bounds__(256) void k_p_update(BlasGrid bg, const Scal* sc, c
     }
 }
 
-// s = r - alpha v
+// s = r - alpha v with alpha = rho / <rhat, v> formed from the partials of
+// the D-apply that produced v.  Every workgroup forms the same alpha; the
+// first records it, with <rhat, v> and the breakdown flag, for later kernels
+// and the host.
 template <int P>
-__global__ __launch_bounds__(256) void k_s_update(BlasGrid bg, const Scal* sc, const void* r_, const void* v_,
-                                                   void* s_) {
+__global__ __launch_bounds__(256) void k_s_update_fin(BlasGrid bg, Scal* sc, const double* pv, int Gv,
+                                                       const void* r_, const void* v_, void* s_) {
     using E = typename Vec<P>::E;
     BLAS_PROLOGUE
-    const Scal& S = sc[rhs];
-    if (!S.active) return;
-    const double ar = S.alpha[0], ai = S.alpha[1];
+    Scal* S = sc + rhs;
+    if (!S->active) return;   // uniform over the workgroup
+    double tv[3];
+    partial_total(pv, Gv, rhs, tv);
+    const double rho[2] = {S->rho[0], S->rho[1]};
+    double ar, ai;
+    const bool bd = alpha_step(rho, tv, ar, ai);
+    if (wg == 0 && threadIdx.x == 0) {
+        S->rv[0] = tv[0];
+        S->rv[1] = tv[1];
+        S->alpha[0] = ar;
+        S->alpha[1] = ai;
+        if (bd) S->breakdown = 1;
+    }
     const E* r = (const E*)r_ + base;
     const E* v = (const E*)v_ + base;
     E* s = (E*)s_ + base;
     BLAS_FOR(k) s[k] = r[k] - cm(ar, ai, v[k]);
 }
 
-// x += alpha p^ + omega s^;  r = s - omega t;  partials <rhat, r>, |r|^2
+// x += alpha p^ + omega s^;  r = s - omega t;  partials of <rhat, r>, |r|^2.
+// omega = <t, s> / <t, t> is formed from the partials of the D-apply that
+// produced t (recorded by the first workgroup).  The new partials go to a
+// second buffer, because other workgroups still read pw.
 template <int P>
-__global__ __launch_bounds__(256) void k_xr_update(BlasGrid bg, const Scal* sc, void* x_, const void* ph_,
-                                                    const void* sh_, const void* s_, const void* t_, void* r_,
-                                                    const void* rh_, double* partial) {
+__global__ __launch_bounds__(256) void k_xr_update_fin(BlasGrid bg, Scal* sc, const double* pw, int Gw, void* x_,
+                                                        const void* ph_, const void* sh_, const void* s_,
+                                                        const void* t_, void* r_, const void* rh_, double* partial) {
     using E = typename Vec<P>::E;
     BLAS_PROLOGUE
-    const Scal& S = sc[rhs];
+    Scal* S = sc + rhs;
     double d[3] = {0, 0, 0};
-    if (S.active) {
-        const double ar = S.alpha[0], ai = S.alpha[1], wr = S.omega[0], wi = S.omega[1];
+    if (S->active) {   // uniform over the workgroup
+        double tw[3];
+        partial_total(pw, Gw, rhs, tw);
+        double wr, wi;
+        omega_step(tw, wr, wi);
+        if (wg == 0 && threadIdx.x == 0) {
+            S->tt = tw[2];
+            S->omega[0] = wr;
+            S->omega[1] = wi;
+        }
+        const double ar = S->alpha[0], ai = S->alpha[1];
         E* x = (E*)x_ + base;
         const E* ph = (const E*)ph_ + base;
         const E* sh = (const E*)sh_ + base;
@@ -225,50 +302,11 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partial, int G, 
     // that of the partial sums
     Scal S;
     if (threadIdx.x == 0) S = sc[rhs];
-    // each thread sums its partials in ascending order, four loads in flight
-    double d[3] = {0, 0, 0};
-    const double* q = partial + 3 * (size_t)rhs * G;
-    int k = threadIdx.x;
-    for (; k + 3 * 256 < G; k += 4 * 256) {
-        double v[4][3];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) v[u][c] = q[3 * (k + 256 * u) + c];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) d[c] += v[u][c];
-    }
-    for (; k < G; k += 256)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) d[c] += q[3 * k + c];
-    __shared__ double tot[3];
-    block_reduce3(d, tot);   // thread 0 writes tot and is the only reader
+    double t[3];
+    partial_total(partial, G, rhs, t);
     if (threadIdx.x != 0 || !S.active) return;
-    const double s0 = tot[0], s1 = tot[1], s2 = tot[2];
+    const double s0 = t[0], s1 = t[1], s2 = t[2];
     switch (kind) {
-        case FIN_ALPHA: {  // alpha = rho / <rhat, v>
-            S.rv[0] = s0;
-            S.rv[1] = s1;
-            if (s0 == 0.0 && s1 == 0.0) {
-                S.alpha[0] = S.alpha[1] = 0.0;
-                S.breakdown = 1;
-            } else {
-                cdiv(S.rho[0], S.rho[1], s0, s1, S.alpha[0], S.alpha[1]);
-            }
-            break;
-        }
-        case FIN_OMEGA: {  // omega = <t, s> / <t, t>; partial was <s, t>
-            S.tt = s2;
-            if (s2 > 0.0) {
-                S.omega[0] = s0 / s2;
-                S.omega[1] = -s1 / s2;
-            } else {
-                S.omega[0] = S.omega[1] = 0.0;
-            }
-            break;
-        }
         case FIN_RHO: {  // rho_old = rho; rho = <rhat, r>; rr = |r|^2
             S.rho_old[0] = S.rho[0];
             S.rho_old[1] = S.rho[1];
@@ -320,14 +358,15 @@ int blas_p_update(int prec, int64_t V, int nrhs, const Scal* sc, const void* r, 
     DISPATCH_P(prec, k_p_update, sc, r, p, v);
     return WCL_OK;
 }
-int blas_s_update(int prec, int64_t V, int nrhs, const Scal* sc, const void* r, const void* v, void* s,
-                  hipStream_t st) {
-    DISPATCH_P(prec, k_s_update, sc, r, v, s);
+int blas_s_update_fin(int prec, int64_t V, int nrhs, Scal* sc, const double* pv, int Gv, const void* r,
+                      const void* v, void* s, hipStream_t st) {
+    DISPATCH_P(prec, k_s_update_fin, sc, pv, Gv, r, v, s);
     return WCL_OK;
 }
-int blas_xr_update(int prec, int64_t V, int nrhs, const Scal* sc, void* x, const void* ph, const void* sh,
-                   const void* s, const void* t, void* r, const void* rh, double* partial, hipStream_t st) {
-    DISPATCH_P(prec, k_xr_update, sc, x, ph, sh, s, t, r, rh, partial);
+int blas_xr_update_fin(int prec, int64_t V, int nrhs, Scal* sc, const double* pw, int Gw, void* x, const void* ph,
+                       const void* sh, const void* s, const void* t, void* r, const void* rh, double* partial,
+                       hipStream_t st) {
+    DISPATCH_P(prec, k_xr_update_fin, sc, pw, Gw, x, ph, sh, s, t, r, rh, partial);
     return WCL_OK;
 }
 int blas_dot(int prec, int64_t V, int nrhs, const Scal* sc, const void* a, const void* b, double* partial,

@@ -41,15 +41,20 @@ int dslash_partials_per_rhs(int V, int lps);
 int launch_dslash(const DslashArgs& a, int gp, int spi, int spo, int epi, int spy, hipStream_t st);
 
 // ------------------------------------------------------------- solvers --
-enum { FIN_ALPHA = 0, FIN_OMEGA = 1, FIN_RHO = 2, FIN_PP = 3, FIN_RR = 4, FIN_RR0 = 5 };
+enum { FIN_RHO = 2, FIN_PP = 3, FIN_RR = 4, FIN_RR0 = 5 };
 
 int blas_partials(int prec, int64_t V);
 int blas_p_update(int prec, int64_t V, int nrhs, const Scal* sc, const void* r, void* p, const void* v,
                   hipStream_t st);
-int blas_s_update(int prec, int64_t V, int nrhs, const Scal* sc, const void* r, const void* v, void* s,
-                  hipStream_t st);
-int blas_xr_update(int prec, int64_t V, int nrhs, const Scal* sc, void* x, const void* ph, const void* sh,
-                   const void* s, const void* t, void* r, const void* rh, double* partial, hipStream_t st);
+// s = r - alpha v, alpha formed from the partials pv of <rhat, v> (Gv per rhs)
+int blas_s_update_fin(int prec, int64_t V, int nrhs, Scal* sc, const double* pv, int Gv, const void* r,
+                      const void* v, void* s, hipStream_t st);
+// x += alpha p^ + omega s^, r = s - omega t, partials of <rhat, r>, |r|^2 into
+// `partial` (which must not alias pw); omega formed from the partials pw of
+// <s, t>, |t|^2 (Gw per rhs)
+int blas_xr_update_fin(int prec, int64_t V, int nrhs, Scal* sc, const double* pw, int Gw, void* x, const void* ph,
+                       const void* sh, const void* s, const void* t, void* r, const void* rh, double* partial,
+                       hipStream_t st);
 int blas_dot(int prec, int64_t V, int nrhs, const Scal* sc, const void* a, const void* b, double* partial,
              hipStream_t st);
 // x = p = v = 0, r = rhat = b, partials of <b, b> for the active rhs

@@ -110,7 +110,7 @@ size_t nested_workspace_bytes(const wcl_lattice* lat, const wcl_solver_params* p
         }
     }
     const size_t partials = (size_t)24 * nrhs * ((lat->V + 63) / 64);
-    return b + 4 * partials + (1 << 20);
+    return b + 6 * partials + (1 << 20);
 }
 
 void wcl_free_workspace(wcl_lattice* lat) {
@@ -321,6 +321,7 @@ struct Engine {
     int Gb, Gd;
     void *r, *rh, *p, *v, *s, *t, *ph, *sh;
     double* partial;
+    double* partial2;   // the x/r update's partials (it reads the D-apply's)
     Scal* d;      // device scalars [nrhs]
     Scal* h;      // pinned host mirror
     Scal* hmap;   // h as the device addresses it (written by the finalize kernels)
@@ -350,6 +351,7 @@ struct Engine {
             sh = s;
         }
         WCL_CHECK(ws->get(name("partial"), (size_t)24 * nrhs * std::max(Gb, Gd), (void**)&partial));
+        WCL_CHECK(ws->get(name("partial2"), (size_t)24 * nrhs * Gb, (void**)&partial2));
         WCL_CHECK(ws->get(name("scal"), sizeof(Scal) * nrhs, (void**)&d));
         if (!ev) WCL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         return WCL_OK;
@@ -459,13 +461,12 @@ struct Engine {
             for (int i = 0; i < nrhs; ++i) a_now[i] = h[i].active;
             if (K) WCL_CHECK((*K)(p, ph, d, a_now));
             WCL_CHECK(apply_dot(ph, v, rh));
-            WCL_CHECK(blas_finalize(partial, Gd, nrhs, d, FIN_ALPHA, st));
-            WCL_CHECK(blas_s_update(P, V, nrhs, d, r, v, s, st));
+            // alpha and omega are formed inside the updates that use them
+            WCL_CHECK(blas_s_update_fin(P, V, nrhs, d, partial, Gd, r, v, s, st));
             if (K) WCL_CHECK((*K)(s, sh, d, a_now));
             WCL_CHECK(apply_dot(sh, t, s));
-            WCL_CHECK(blas_finalize(partial, Gd, nrhs, d, FIN_OMEGA, st));
-            WCL_CHECK(blas_xr_update(P, V, nrhs, d, x, ph, sh, s, t, r, rh, partial, st));
-            WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RHO, st, hmap));
+            WCL_CHECK(blas_xr_update_fin(P, V, nrhs, d, partial, Gd, x, ph, sh, s, t, r, rh, partial2, st));
+            WCL_CHECK(blas_finalize(partial2, Gb, nrhs, d, FIN_RHO, st, hmap));
             WCL_HIP(hipEventRecord(ev, st));
             if (it < max_iter) {
                 WCL_CHECK(blas_p_update(P, V, nrhs, d, r, p, v, st));
