@@ -157,9 +157,21 @@ __global__ __launch_bounds__(256) void k_s_update_fin(BlasGrid bg, Scal* sc, con
     BLAS_PROLOGUE
     Scal* S = sc + rhs;
     if (!S->active) return;   // uniform over the workgroup
+    const E* r = (const E*)r_ + base;
+    const E* v = (const E*)v_ + base;
+    E* s = (E*)s_ + base;
+    // this thread's first element is requested before the reduction, so that
+    // the two load latencies overlap
+    const int k0 = wg * 256 + threadIdx.x;
+    const bool own0 = k0 < bg.n && (k0 < bg.last || (k0 & 63) < bg.rem);
+    E r0{}, v0{};
+    if (own0) {
+        r0 = r[k0];
+        v0 = v[k0];
+    }
+    const double rho[2] = {S->rho[0], S->rho[1]};
     double tv[3];
     partial_total(pv, Gv, rhs, tv);
-    const double rho[2] = {S->rho[0], S->rho[1]};
     double ar, ai;
     const bool bd = alpha_step(rho, tv, ar, ai);
     if (wg == 0 && threadIdx.x == 0) {
@@ -169,10 +181,9 @@ __global__ __launch_bounds__(256) void k_s_update_fin(BlasGrid bg, Scal* sc, con
         S->alpha[1] = ai;
         if (bd) S->breakdown = 1;
     }
-    const E* r = (const E*)r_ + base;
-    const E* v = (const E*)v_ + base;
-    E* s = (E*)s_ + base;
-    BLAS_FOR(k) s[k] = r[k] - cm(ar, ai, v[k]);
+    if (own0) s[k0] = r0 - cm(ar, ai, v0);
+    for (int k = k0 + step; k < bg.n; k += step)
+        if (k < bg.last || (k & 63) < bg.rem) s[k] = r[k] - cm(ar, ai, v[k]);
 }
 
 // x += alpha p^ + omega s^;  r = s - omega t;  partials of <rhat, r>, |r|^2.
@@ -188,6 +199,26 @@ __global__ __launch_bounds__(256) void k_xr_update_fin(BlasGrid bg, Scal* sc, co
     Scal* S = sc + rhs;
     double d[3] = {0, 0, 0};
     if (S->active) {   // uniform over the workgroup
+        E* x = (E*)x_ + base;
+        const E* ph = (const E*)ph_ + base;
+        const E* sh = (const E*)sh_ + base;
+        const E* s = (const E*)s_ + base;
+        const E* t = (const E*)t_ + base;
+        E* r = (E*)r_ + base;
+        const E* rh = (const E*)rh_ + base;
+        // this thread's first element is requested before the reduction
+        const int k0 = wg * 256 + threadIdx.x;
+        const bool own0 = k0 < bg.n && (k0 < bg.last || (k0 & 63) < bg.rem);
+        E x0{}, ph0{}, sh0{}, s0{}, t0{}, rh0{};
+        if (own0) {
+            x0 = x[k0];
+            ph0 = ph[k0];
+            sh0 = sh[k0];
+            s0 = s[k0];
+            t0 = t[k0];
+            rh0 = rh[k0];
+        }
+        const double ar = S->alpha[0], ai = S->alpha[1];
         double tw[3];
         partial_total(pw, Gw, rhs, tw);
         double wr, wi;
@@ -197,20 +228,19 @@ __global__ __launch_bounds__(256) void k_xr_update_fin(BlasGrid bg, Scal* sc, co
             S->omega[0] = wr;
             S->omega[1] = wi;
         }
-        const double ar = S->alpha[0], ai = S->alpha[1];
-        E* x = (E*)x_ + base;
-        const E* ph = (const E*)ph_ + base;
-        const E* sh = (const E*)sh_ + base;
-        const E* s = (const E*)s_ + base;
-        const E* t = (const E*)t_ + base;
-        E* r = (E*)r_ + base;
-        const E* rh = (const E*)rh_ + base;
-        BLAS_FOR(k) {
-            x[k] = x[k] + cm(ar, ai, ph[k]) + cm(wr, wi, sh[k]);
-            E nr = s[k] - cm(wr, wi, t[k]);
-            r[k] = nr;
-            dot_acc(rh[k], nr, d);
+        if (own0) {
+            x[k0] = x0 + cm(ar, ai, ph0) + cm(wr, wi, sh0);
+            E nr = s0 - cm(wr, wi, t0);
+            r[k0] = nr;
+            dot_acc(rh0, nr, d);
         }
+        for (int k = k0 + step; k < bg.n; k += step)
+            if (k < bg.last || (k & 63) < bg.rem) {
+                x[k] = x[k] + cm(ar, ai, ph[k]) + cm(wr, wi, sh[k]);
+                E nr = s[k] - cm(wr, wi, t[k]);
+                r[k] = nr;
+                dot_acc(rh[k], nr, d);
+            }
     }
     block_reduce3(d, partial + 3 * ((size_t)rhs * bg.G + wg));
 }
