@@ -1,19 +1,18 @@
 """Benchmark: time-to-solution of the mixed-precision nested RAS-BiCGStab
 solver on one MI355X, beside the plain FP64 BiCGStab on the same GPU, plus
-the Wilson-clover D-apply against the HBM roofline, the 12-source batched
-solve, the 32^4 FP16-storage solve and the serving loop.
+the Wilson-clover D-apply against the HBM roofline, the 16^3x32 solves, the
+12-source batched solve, the paper's 32^4 experiment and the serving loop.
 
 One step = one complete solve of D phi = eta to |eta - D phi|/|eta| <= 1e-10 on
-  16^3 x 32, random SU(3) links exp(i eps H), eps = 0.5 (seed 1),
+  32^4 (1 048 576 sites), random SU(3) links exp(i eps H), eps = 0.3 (seed 1),
   kappa = 0.125, c_sw = 1.0, Gaussian source (seed 2);
-  FP64 outer / FP32 inner BiCGStab right-preconditioned by RAS
-  (N_dominv = 4 minimal-residual steps per sweep).  The domain shape, overlap,
-  storage, sweeps and inner tolerance are picked by the library's autotuner
-  before the timed region; the literal 8^4 (s = 0 and s = 1) domain solves are
-  timed beside it.
+  FP64 outer / FP32 inner BiCGStab right-preconditioned by RAS with FP16
+  storage.  The domain shape ({4^4, 4^3x8, 8^4}), overlap, sweeps, N_dominv
+  and inner tolerance are picked by the library's autotuner before the timed
+  region, timing solves of a different source (seed 7).
 Inputs are resident in HBM before every timed region.
 
-Prints one JSON line; --mode selects a single section (dapply, copyref, serve).
+Prints one JSON line; --mode selects a single section.
 """
 from __future__ import annotations
 
@@ -52,23 +51,27 @@ def parse():
     ap.add_argument("--mode", default="full", choices=["full", "dapply", "copyref", "serve", "solve", "sweep", "paper"],
                     help="dapply: only the 32^4 FP32 D-apply loop; copyref: a 1 GiB device copy "
                          "(the reference kernel for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE); serve: only the "
-                         "serving run; solve: K timed 16^3x32 solves with the RAS parameters given below "
+                         "serving run; solve: K timed solves on --lattice with the RAS parameters given below "
                          "(no autotuning), for kernel traces; sweep: 55 launches of one RAS sweep (NRAS = 1) of the "
-                         "on-chip domain solver with those parameters, for counters; paper: the paper's 32^4 "
-                         "x-split table with the NRAS x N_dominv scan")
+                         "on-chip domain solver with those parameters (NRAS = 2 with --n-ras 2), for counters; "
+                         "paper: the paper's 32^4 x-split table with the NRAS x N_dominv scan")
+    ap.add_argument("--lattice", default="32x32x32x32", help="solve/sweep modes: lattice extents")
+    ap.add_argument("--eps", type=float, default=0.3, help="solve/sweep modes: gauge-field eps")
     ap.add_argument("--block", default="4x4x4x4", help="solve mode: domain shape")
     ap.add_argument("--overlap", type=int, default=0, help="solve mode: overlap s")
     ap.add_argument("--storage", default="f16", choices=["f32", "f16"], help="solve mode: RAS storage")
     ap.add_argument("--dapply-prec", default="f32", choices=["f64", "f32", "f16"], help="dapply mode: precision")
     ap.add_argument("--n-ras", type=int, default=3)
-    ap.add_argument("--n-dominv", type=int, default=4)
-    ap.add_argument("--tol-inner", type=float, default=1e-4)
+    ap.add_argument("--n-dominv", type=int, default=5)
+    ap.add_argument("--tol-inner", type=float, default=1e-5)
+    ap.add_argument("--timers", action="store_true", help="solve mode: per-category HIP-event timers")
     ap.add_argument("--point-sources", action="store_true", help="solve mode: the 12 point sources in one batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dapply", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 12-source, 32^4 and serving sections")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's 32^4 x-split table")
+    ap.add_argument("--no-small", action="store_true", help="skip the 16^3x32 and 4^4 sections")
     ap.add_argument("--paper-eps", type=float, default=0.3, help="paper mode: gauge-field eps")
     ap.add_argument("--paper-scan", action="store_true", help="paper mode: add the NRAS x N_dominv scan")
     ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
@@ -81,6 +84,8 @@ DOMAIN_SOURCES = ("wcl_block.hip", "wcl_device.h", "wcl_internal.h")
 # FP32 VALU peak without packed-FP32 instructions (the library is built
 # without them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
 VALU_F32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# MI355X's published FP32 vector peak (it counts packed-FP32 instructions)
+FP32_PEAK_PUBLISHED_TFLOPS = 157.3
 # flops of the Wilson-clover operator per site: site term (two 6x6 Hermitian
 # mat-vecs + the combination) and one hop (projection, two SU(3) mat-vecs,
 # accumulation); 552 + 8 x 165 = 1872
@@ -175,22 +180,6 @@ def timed_solves(torch, lat, params, kappa, csw, e, phi, steps, warmup, nrhs=1):
     return (time.perf_counter() - t0) / steps * 1e3, stats
 
 
-def time_domain_sweep(torch, W, lat, dims, ras, eta, kappa, csw, n=50):
-    """Average duration (HIP events) of one launch of the on-chip domain
-    solver: ras_precondition with NRAS = 1 is exactly one k_blk_fused launch
-    (projection of the FP32 residual, N_dominv MR steps, restriction)."""
-    nb, ev = lat.block_info(ras)
-    one = W.RasParams.make(block=tuple(ras.block), s=ras.s, n_ras=1, n_dominv=ras.n_dominv, storage=ras.storage,
-                           kernel=W.BLOCK_FUSED)
-    r32 = lat.pack(eta, W.F32)
-    v32 = lat.empty(W.F32)
-    for _ in range(5):
-        lat.ras_precondition(one, kappa, csw, r32, v32)
-    torch.cuda.synchronize()
-    us = event_time_us(torch, lambda k: lat.ras_precondition(one, kappa, csw, r32, v32), n)
-    return us, domain_sweep_flops(dims, ras, nb, ev)
-
-
 def paper_table(torch, W, ctx, dims, U, eta, kappa=0.126, csw=1.0, tol=1e-14, n_ras=3, n_dominv=5, scan=False):
     """The paper's benchmark (Sec. 5, Table 1) on one GPU: 32^4 lattice,
     kappa 0.126, c_SW 1.0, |eta - D phi|/|eta| < 1e-14, the nested solver
@@ -206,35 +195,42 @@ def paper_table(torch, W, ctx, dims, U, eta, kappa=0.126, csw=1.0, tol=1e-14, n_
     out = {"lattice": list(dims), "kappa": kappa, "csw": csw, "tol": tol, "domains": list(xb),
            "n_ras": n_ras, "n_dominv": n_dominv}
 
-    def run(p):
+    def run(p, timers=False):
         lat.solve_nested(p, kappa, csw, e, phi, raise_on_notconv=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, st = lat.solve_nested(p, kappa, csw, e, phi, raise_on_notconv=False)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3, st
+        ms = (time.perf_counter() - t0) * 1e3
+        if timers:
+            # the timing chart of Sec. 4 from HIP events in a separate solve
+            p.timers = 1
+            _, stt = lat.solve_nested(p, kappa, csw, e, phi, raise_on_notconv=False)
+            p.timers = 0
+            st = dict(st)
+            st["chart"] = {"T_Dv_calc_ms": round(stt["ms_dslash"], 3), "T_dominv_calc_ms": round(stt["ms_dominv"], 3),
+                           "blas_ms": round(stt["ms_blas"], 3), "host_wait_ms": round(stt["ms_host"], 3),
+                           "total_ms": round(stt["ms_total"], 3)}
+        return ms, st
 
     base = dict(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=1000)
-    ms, st = run(W.SolverParams.make(precond=W.PRECOND_NONE, **base))
+    ms, st = run(W.SolverParams.make(precond=W.PRECOND_NONE, **base), timers=True)
     out["no_prec"] = {"ms": round(ms, 3), "dv_count": st["dslash_full"], "outer_iters": st["outer_iters"],
                       "inner_iters": st["inner_iters"], "true_resid": st["true_resid"],
-                      "converged": bool(st["converged"])}
+                      "converged": bool(st["converged"]), "chart": st["chart"]}
     for s in (0, 1, 2):
         ras = W.RasParams.make(block=xb, s=s, n_ras=n_ras, n_dominv=n_dominv, storage=W.F32)
-        ms, st = run(W.SolverParams.make(ras=ras, **base))
-        # the domain solver alone: one sweep timed with HIP events, times the sweeps of the solve
-        one = W.RasParams.make(block=xb, s=s, n_ras=1, n_dominv=n_dominv, storage=W.F32)
-        r32 = lat.pack(eta, W.F32)
-        v32 = lat.empty(W.F32)
-        lat.ras_precondition(one, kappa, csw, r32, v32)
-        torch.cuda.synchronize()
-        us_sweep = event_time_us(torch, lambda k: lat.ras_precondition(one, kappa, csw, r32, v32), 5)
+        ms, st = run(W.SolverParams.make(ras=ras, **base), timers=True)
         out[f"ras_d{2 * s}"] = {"ms": round(ms, 3), "dv_count": st["dslash_full"], "outer_iters": st["outer_iters"],
                                 "inner_iters": st["inner_iters"], "ras_sweeps": st["ras_sweeps"],
                                 "domain_mr_steps": st["dslash_block"], "true_resid": st["true_resid"],
-                                "converged": bool(st["converged"]),
-                                "dominv_ms_est": round(us_sweep * st["ras_sweeps"] / 1e3, 3)}
-        del r32, v32
+                                "converged": bool(st["converged"]), "chart": st["chart"]}
+    out["paper_table1_context"] = {
+        "hardware": "8 x GTX 285 over Gigabit Ethernet (Sec. 4); kappa 0.126, c_SW 1.0, 32^4, x-only split, 1e-14",
+        "no_prec": {"total_s": 53.305, "dv_count": 1328, "T_Dv_calc_s": 3.900},
+        "ras_d0": {"total_s": 27.977, "dv_count": 484, "T_Dv_calc_s": 1.424, "T_dominv_calc_s": 5.954},
+        "ras_d2": {"total_s": 35.234, "dv_count": 496, "T_Dv_calc_s": 1.436, "T_dominv_calc_s": 6.245},
+        "ras_d4": {"total_s": 37.195, "dv_count": 416, "T_Dv_calc_s": 1.205, "T_dominv_calc_s": 6.993}}
     if scan:
         grid = {}
         for nr in range(1, 11):
@@ -292,15 +288,16 @@ def serve_bench(W, I, np, ctx, n_req, slots):
         sources = list(pool.map(lambda i: I.gaussian_source(SERVE_SIZES[kind[i]], 1000 + int(i)), range(n_req)))
     log("serving: sources generated")
 
-    def run(budget, arrivals):
-        srv = W.Server(ctx, max_slots=slots, hbm_budget=budget)
+    def run(budget, arrivals, nslots):
+        srv = W.Server(ctx, max_slots=nslots, hbm_budget=budget)
         for k, d in enumerate(SERVE_SIZES):
             srv.register_gauge(k, d, gauges[k])
         free = {k: [] for k in range(len(SERVE_SIZES))}   # solution buffers returned by finished requests
+        kept = {}   # one finished request per lattice size, kept for the oracle check
         inflight, done = {}, []
         nxt, late = 0, 0
         t0 = time.monotonic()
-        window = 2 * slots
+        window = 2 * nslots
         while len(done) < n_req:
             while nxt < n_req:
                 if arrivals is None and len(inflight) >= window:
@@ -318,7 +315,10 @@ def serve_bench(W, I, np, ctx, n_req, slots):
                 r = srv.poll(t)
                 if r is not None:
                     i = inflight.pop(t)
-                    free[int(kind[i])].append(r[0])
+                    k = int(kind[i])
+                    if k not in kept:
+                        kept[k] = (i, r[0].copy())
+                    free[k].append(r[0])
                     done.append((i, r[1]))
             time.sleep(0.0005)
         T = time.monotonic() - t0
@@ -339,18 +339,135 @@ def serve_bench(W, I, np, ctx, n_req, slots):
         return {"requests": n_req, "seconds": round(T, 3), "solves_per_s": round(n_req / T, 3),
                 "p50_ms": round(pct(lat_ms, 50), 3), "p99_ms": round(pct(lat_ms, 99), 3),
                 "service_p50_ms": round(pct(svc_ms, 50), 3), "admission_wait_p99_ms": round(pct(wait_ms, 99), 3),
-                "failed": len(bad), "late_submits": late, "per_size": per_size}
+                "failed": len(bad), "late_submits": late, "per_size": per_size}, kept
 
-    closed = run(0, None)
+    # one slot: requests run one after another (no overlap on the device)
+    single, _ = run(0, None, 1)
+    log(f"serving: one slot {single['solves_per_s']} solves/s")
+    closed, kept = run(0, None, slots)
     log(f"serving: closed loop {closed['solves_per_s']} solves/s")
+    # one request of every lattice size checked by the oracle's own operator
+    from oracle import Oracle
+    check = {}
+    for k, (i, sol) in sorted(kept.items()):
+        o = Oracle(SERVE_SIZES[k], gauges[k], precompute_clover=False)
+        res = float(np.linalg.norm(sources[i] - o.apply_D(sol, float(kappa[i]), float(csw[i])))
+                    / np.linalg.norm(sources[i]))
+        check["x".join(map(str, SERVE_SIZES[k]))] = {"request": int(i), "kappa": round(float(kappa[i]), 6),
+                                                     "csw": float(csw[i]), "true_resid_by_oracle": res}
+        del o
+    log(f"serving: oracle check {check}")
     lam = 0.8 * closed["solves_per_s"]
     arrivals = np.cumsum(gaps) / lam
-    opened = run(24 << 30, arrivals)
+    opened, _ = run(24 << 30, arrivals, slots)
     opened["rate_per_s"] = round(lam, 3)
     opened["hbm_budget_bytes"] = 24 << 30
     log(f"serving: Poisson p50 {opened['p50_ms']} ms p99 {opened['p99_ms']} ms")
-    return {"closed_loop": closed, "poisson": opened, "slots": slots,
+    return {"closed_loop": closed, "closed_loop_one_slot": single,
+            "overlap_gain": round(closed["solves_per_s"] / single["solves_per_s"], 3), "poisson": opened,
+            "slots": slots, "oracle_check": check,
             "mix": {"x".join(map(str, d)): wt for d, wt in zip(SERVE_SIZES, SERVE_WEIGHTS)}}
+
+
+def roofline_alu(achieved_tflops, kernel, us, traffic, flops):
+    """ALU-bound roofline entry: against the published FP32 vector peak and
+    against the peak without packed-FP32 instructions (the library is built
+    without them)."""
+    return {"bound": "alu", "achieved": round(achieved_tflops, 2), "peak": FP32_PEAK_PUBLISHED_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_PEAK_PUBLISHED_TFLOPS, 4), "traffic": traffic,
+            "peak_without_packed_fp32": round(VALU_F32_PEAK_TFLOPS, 1),
+            "frac_without_packed_fp32": round(achieved_tflops / VALU_F32_PEAK_TFLOPS, 4),
+            "kernel": kernel, "us_per_launch": round(us, 2), "flops_per_launch": flops}
+
+
+def residual_hop_flops(dims, ras, nblocks, ev):
+    """Flops of the residual update a later sweep forms before its MR steps:
+    without overlap only the hops that leave the domain (each 165 flops) plus
+    the subtraction; with overlap the whole operator on every extended site."""
+    no_overlap = ras.s == 0 or all(ras.block[m] == dims[m] for m in range(4))
+    if no_overlap:
+        cross = sum(2.0 / ras.block[m] for m in range(4) if ras.block[m] < dims[m])
+        return (HOP_FLOPS * cross + 24) * nblocks * ev
+    return (SITE_TERM_FLOPS + 8 * HOP_FLOPS + 24) * nblocks * ev
+
+
+def domain_kernel_rooflines(torch, W, lat, dims, ras, eta, kappa, csw, stats, n=30):
+    """The domain solver's two kernel instantiations in a solve: the first
+    sweep (projection, N_dominv MR steps, restriction) and the later sweeps
+    (the same plus the residual update of the previous sweep).  One sweep is
+    timed alone with HIP events (ras_precondition, NRAS = 1); a later sweep's
+    launch is the difference of NRAS = 2 and NRAS = 1.  Returns the entry of
+    the instantiation that takes the larger share of the solve first."""
+    nb, ev = lat.block_info(ras)
+    if ev > 256:
+        return None, None
+    r32 = lat.pack(eta, W.F32)
+    v32 = lat.empty(W.F32)
+    out = {}
+    for nr in (1, 2):
+        p = W.RasParams.make(block=tuple(ras.block), s=ras.s, n_ras=nr, n_dominv=ras.n_dominv, storage=ras.storage,
+                             kernel=W.BLOCK_FUSED)
+        for _ in range(5):
+            lat.ras_precondition(p, kappa, csw, r32, v32)
+        torch.cuda.synchronize()
+        out[nr] = event_time_us(torch, lambda k: lat.ras_precondition(p, kappa, csw, r32, v32), n)
+    del r32, v32
+    fl0 = domain_sweep_flops(dims, ras, nb, ev)
+    fl1 = fl0 + residual_hop_flops(dims, ras, nb, ev)
+    t0, t1 = out[1], out[2] - out[1]
+    sweeps = stats["ras_sweeps"]
+    first = sweeps / max(1, ras.n_ras)
+    later = sweeps - first
+    st = {1: "f32", 2: "f16"}[ras.storage]
+    shape = "x".join(map(str, ras.block))
+    key = f"fused_{shape}_s{ras.s}_nd{ras.n_dominv}_{st}"
+    res = "res2" if ras.s == 0 else "res1"
+    e_first = roofline_alu(fl0 / t0 / 1e6, f"k_blk_fused<{st},res0> (first sweep: {nb} domains x {ev} sites x "
+                           f"{ras.n_dominv} MR steps on chip, {fl0 / 1e9:.3f} GFLOP per launch; {first:.0f} launches "
+                           f"per solve)", t0, measured_traffic("domain_counters.json", DOMAIN_SOURCES, key, lat.V),
+                           fl0)
+    e_later = roofline_alu(fl1 / t1 / 1e6, f"k_blk_fused<{st},{res}> (later sweeps: residual update of the previous "
+                           f"sweep, then {ras.n_dominv} MR steps on {nb} domains x {ev} sites, {fl1 / 1e9:.3f} GFLOP "
+                           f"per launch; {later:.0f} launches per solve; duration = NRAS 2 minus NRAS 1)", t1,
+                           measured_traffic("domain_counters.json", DOMAIN_SOURCES, key + "_" + res, lat.V), fl1)
+    e_first["share_of_solve_ms"] = round(first * t0 / 1e3, 3)
+    e_later["share_of_solve_ms"] = round(later * t1 / 1e3, 3)
+    if later * t1 >= first * t0:
+        return e_later, e_first
+    return e_first, e_later
+
+
+def plain_f64(torch, lat, kappa, csw, e, phi, tol, reps=1):
+    lat.solve_bicgstab_f64(tol, 100000, kappa, csw, e, phi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, st = lat.solve_bicgstab_f64(tol, 100000, kappa, csw, e, phi)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps * 1e3, st
+
+
+def timers_desc(st):
+    return {k: round(st[k], 3) for k in ("ms_total", "ms_dslash", "ms_dominv", "ms_blas", "ms_host")}
+
+
+def oracle_resid(Oracle, np, dims, U, eta, sol, kappa, csw):
+    """|eta - D sol| / |eta| with the oracle's own operator (clover on the fly)."""
+    o = Oracle(dims, U, precompute_clover=False)
+    r = float(np.linalg.norm(eta - o.apply_D(sol, kappa, csw)) / np.linalg.norm(eta))
+    del o
+    return r
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
@@ -378,8 +495,9 @@ def main():
                           "ms_per_copy": ms, "GBps_read_plus_write": 2 * n / ms / 1e6}))
         return
     ctx = W.Context(0)
+    big = (32, 32, 32, 32)
+    kappa, csw, tol = 0.125, 1.0, 1e-10
     if args.mode == "dapply":
-        big = (32, 32, 32, 32)
         lb = W.Lattice(ctx, big)
         lb.upload_gauge(I.random_gauge(big, 1.0, 1))
         prec = {"f64": 0, "f32": 1, "f16": 2}[args.dapply_prec]
@@ -390,7 +508,6 @@ def main():
         ctx.close()
         return
     if args.mode == "paper":
-        big = (32, 32, 32, 32)
         tab = paper_table(torch, W, ctx, big, I.random_gauge(big, args.paper_eps, 1), I.gaussian_source(big, 2),
                           scan=args.paper_scan)
         tab["eps"] = args.paper_eps
@@ -401,146 +518,163 @@ def main():
         print(json.dumps({"mode": "serve", "serving": serve_bench(W, I, np, ctx, args.requests, args.slots)}))
         ctx.close()
         return
+    if args.mode in ("sweep", "solve"):
+        dims = tuple(int(v) for v in args.lattice.split("x"))
+        lat = W.Lattice(ctx, dims)
+        lat.upload_gauge(I.random_gauge(dims, args.eps, 1))
+        storage = W.F16 if args.storage == "f16" else W.F32
+        block = tuple(int(v) for v in args.block.split("x"))
+        if args.mode == "sweep":
+            eta = I.gaussian_source(dims, 2)
+            ras = W.RasParams.make(block=block, s=args.overlap, n_ras=args.n_ras, n_dominv=args.n_dominv,
+                                   storage=storage, kernel=W.BLOCK_FUSED)
+            r32 = lat.pack(eta, W.F32)
+            v32 = lat.empty(W.F32)
+            for _ in range(5):
+                lat.ras_precondition(ras, kappa, csw, r32, v32)
+            torch.cuda.synchronize()
+            us = event_time_us(torch, lambda k: lat.ras_precondition(ras, kappa, csw, r32, v32), 50)
+            print(json.dumps({"mode": "sweep", "lattice": list(dims), "us": us,
+                              "ras": ras_desc(W.SolverParams.make(ras=ras))}))
+        else:
+            nrhs = 12 if args.point_sources else 1
+            src = I.point_sources(dims, 3)[1] if args.point_sources else I.gaussian_source(dims, 2)
+            e = lat.pack(src, W.F64, nrhs)
+            phi = lat.zeros(W.F64, nrhs)
+            p = W.SolverParams.make(tol_outer=tol, tol_inner=args.tol_inner, max_outer=200, max_inner=100,
+                                    timers=int(args.timers),
+                                    ras=W.RasParams.make(block=block, s=args.overlap, n_ras=args.n_ras,
+                                                         n_dominv=args.n_dominv, storage=storage))
+            ms, sts = timed_solves(torch, lat, p, kappa, csw, e, phi, args.steps, args.warmup, nrhs)
+            print(json.dumps({"mode": "solve", "lattice": list(dims), "ms": ms, "nrhs": nrhs, "ras": ras_desc(p),
+                              "stats": stats_desc(sts[-1]), "timers": timers_desc(sts[-1])}))
+        lat.close()
+        ctx.close()
+        return
 
-    dims = (16, 16, 16, 32)
-    kappa, csw, tol = 0.125, 1.0, 1e-10
-    if args.mode == "sweep":
-        lat = W.Lattice(ctx, dims)
-        lat.upload_gauge(I.random_gauge(dims, 0.5, 1))
-        eta = I.gaussian_source(dims, 2)
-        ras = W.RasParams.make(block=tuple(int(v) for v in args.block.split("x")), s=args.overlap,
-                               n_dominv=args.n_dominv, storage=W.F16 if args.storage == "f16" else W.F32)
-        us, fl = time_domain_sweep(torch, W, lat, dims, ras, eta, kappa, csw)
-        ras.n_ras = 1
-        print(json.dumps({"mode": "sweep", "us": us, "flops": fl, "ras": ras_desc(W.SolverParams.make(ras=ras))}))
-        lat.close()
-        ctx.close()
-        return
-    if args.mode == "solve":
-        lat = W.Lattice(ctx, dims)
-        lat.upload_gauge(I.random_gauge(dims, 0.5, 1))
-        nrhs = 12 if args.point_sources else 1
-        src = I.point_sources(dims, 3)[1] if args.point_sources else I.gaussian_source(dims, 2)
-        e = lat.pack(src, W.F64, nrhs)
-        phi = lat.zeros(W.F64, nrhs)
-        p = W.SolverParams.make(tol_outer=tol, tol_inner=args.tol_inner, max_outer=200, max_inner=100,
-                                ras=W.RasParams.make(block=tuple(int(v) for v in args.block.split("x")),
-                                                     s=args.overlap, n_ras=args.n_ras, n_dominv=args.n_dominv,
-                                                     storage=W.F16 if args.storage == "f16" else W.F32))
-        ms, sts = timed_solves(torch, lat, p, kappa, csw, e, phi, args.steps, args.warmup, nrhs)
-        print(json.dumps({"mode": "solve", "ms": ms, "nrhs": nrhs, "ras": ras_desc(p), "stats": stats_desc(sts[-1])}))
-        lat.close()
-        ctx.close()
-        return
-    lat = W.Lattice(ctx, dims)
-    U = I.random_gauge(dims, 0.5, 1)
-    lat.upload_gauge(U)
-    eta = I.gaussian_source(dims, 2)
-    e = lat.pack(eta, W.F64)
+    # ================= the headline: 32^4, eps 0.3, FP16-storage RAS, autotuned
+    U32 = {0.3: I.random_gauge(big, 0.3, 1)}
+    eta32 = I.gaussian_source(big, 2)
+    tune_src32 = I.gaussian_source(big, 7)
+    lat = W.Lattice(ctx, big)
+    lat.upload_gauge(U32[0.3])
+    e = lat.pack(eta32, W.F64)
+    et = lat.pack(tune_src32, W.F64)
     phi = lat.zeros(W.F64)
-    log("16^3x32 fields resident")
-
-    # ---- autotuner (not timed): domain shape, overlap, storage, sweeps, N_dominv, inner tolerance
-    base = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=100)
+    log("32^4 fields resident")
+    base16 = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=100,
+                                 ras=W.RasParams.make(block=(4, 4, 4, 4), storage=W.F16))
     t0 = time.perf_counter()
-    tuned, tuned_ms = W.autotune(lat, base, kappa, csw, e, 1)
+    tuned, _ = W.autotune(lat, base16, kappa, csw, et, 1, storage=W.F16)
     tune_s = time.perf_counter() - t0
-    log(f"autotuned in {tune_s:.1f} s: {ras_desc(tuned)}")
-
-    # ---- the timed steps: K complete solves with the tuned parameters
+    del et
+    log(f"autotuned in {tune_s:.1f} s on the seed-7 source: {ras_desc(tuned)}")
     ms_per_step, stats = timed_solves(torch, lat, tuned, kappa, csw, e, phi, args.steps, args.warmup)
     true_res = max(st["true_resid"] for st in stats)
-    sol = lat.unpack(phi, W.F64)
+    sol32 = lat.unpack(phi, W.F64)
     log(f"headline solve {ms_per_step:.3f} ms")
-
-    # ---- the dominant kernel of the step: the on-chip domain solver, one
-    # sweep (NRAS = 1) of the tuned domains, timed with HIP events
-    roof_dom = None
-    nb, ev = lat.block_info(tuned.ras)
-    if ev <= 256:   # the fused (on-chip) domain solver
-        us_dom, fl = time_domain_sweep(torch, W, lat, dims, tuned.ras, eta, kappa, csw)
-        tf = fl / us_dom / 1e6
-        key = "fused_" + "x".join(map(str, tuned.ras.block)) + f"_s{tuned.ras.s}_nd{tuned.ras.n_dominv}_" + \
-              {1: "f32", 2: "f16"}[tuned.ras.storage]
-        roof_dom = {"bound": "alu", "achieved": round(tf, 2), "peak": round(VALU_F32_PEAK_TFLOPS, 1),
-                    "unit": "TFLOP/s", "frac": round(tf / VALU_F32_PEAK_TFLOPS, 4),
-                    "traffic": measured_traffic("domain_counters.json", DOMAIN_SOURCES, key, lat.V),
-                    "kernel": f"k_blk_fused (one RAS sweep: {nb} domains x {ev} sites x {tuned.ras.n_dominv} MR steps "
-                              f"on chip, {fl / 1e9:.3f} GFLOP per launch)", "us_per_launch": round(us_dom, 2)}
-        log(f"domain sweep {us_dom:.1f} us, {tf:.1f} TFLOP/s")
-
-    # ---- the literal 8^4-domain configurations, s = 0 and s = 1
-    literal = {}
-    for s in (0, 1):
-        p = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=100,
-                                ras=W.RasParams.make(block=(8, 8, 8, 8), s=s, n_ras=3, n_dominv=4, storage=W.F32))
-        ms, sts = timed_solves(torch, lat, p, kappa, csw, e, phi, max(2, args.steps // 2), 1)
-        literal[f"8x8x8x8_s{s}"] = {"ms": round(ms, 3), "stats": stats_desc(sts[-1])}
-        log(f"8^4 s={s}: {ms:.3f} ms")
-
-    # ---- plain FP64 BiCGStab on the same GPU and input
-    for _ in range(args.warmup):
-        lat.solve_bicgstab_f64(tol, 100000, kappa, csw, e, phi)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, pst = lat.solve_bicgstab_f64(tol, 100000, kappa, csw, e, phi)
-    torch.cuda.synchronize()
-    plain_ms = (time.perf_counter() - t0) / args.steps * 1e3
-    log(f"plain FP64 {plain_ms:.3f} ms")
-
-    # ---- the 4^4 plain-method anchor (eps 0.5, kappa 0.12): launch-bound FP64 BiCGStab
-    small = None
-    if not args.no_extra:
-        d4 = (4, 4, 4, 4)
-        l4 = W.Lattice(ctx, d4)
-        U4 = I.random_gauge(d4, 0.5, 1)
-        l4.upload_gauge(U4)
-        eta4 = I.gaussian_source(d4, 2)
-        e4, p4 = l4.pack(eta4, W.F64), l4.zeros(W.F64)
-        l4.solve_bicgstab_f64(1e-10, 1000, 0.12, 1.0, e4, p4)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(20):
-            _, st4 = l4.solve_bicgstab_f64(1e-10, 1000, 0.12, 1.0, e4, p4)
-        torch.cuda.synchronize()
-        ms4 = (time.perf_counter() - t0) / 20 * 1e3
-        small = {"lattice": list(d4), "kappa": 0.12, "ms": round(ms4, 3), "iters": st4["outer_iters"],
-                 "true_resid": st4["true_resid"], "us_per_iter": round(ms4 * 1e3 / st4["outer_iters"], 1)}
-        l4.close()
-        log(f"4^4 plain FP64: {small}")
-
-    # ---- 12 spin-colour point sources batched in one solve (same lattice)
-    multi = None
-    if not args.no_extra:
-        x0, eta12 = I.point_sources(dims, 3)
-        e12 = lat.pack(eta12, W.F64, 12)
-        phi12 = lat.zeros(W.F64, 12)
-        # the batch and the single point source are each autotuned for themselves (not timed)
-        tuned12, _ = W.autotune(lat, base, kappa, csw, e12, 12)
-        ms12, st12 = timed_solves(torch, lat, tuned12, kappa, csw, e12, phi12, max(2, args.steps // 2), 1, nrhs=12)
-        p1 = lat.pack(eta12[0], W.F64)
-        f1 = lat.zeros(W.F64)
-        tuned1, _ = W.autotune(lat, base, kappa, csw, p1, 1)
-        ms1, _ = timed_solves(torch, lat, tuned1, kappa, csw, p1, f1, max(2, args.steps // 2), 1)
-        multi = {"rhs": 12, "source_site": x0, "ms_per_batch": round(ms12, 3),
-                 "solves_per_s": round(12e3 / ms12, 2), "ms_single_point_source": round(ms1, 3),
-                 "per_rhs_cost_vs_single": round(ms12 / 12 / ms1, 3),
-                 "max_true_resid": st12[-1]["true_resid"], "ras_batch": ras_desc(tuned12),
-                 "ras_single": ras_desc(tuned1), "stats": stats_desc(st12[-1])}
-        del e12, phi12, p1, f1
-        log(f"12 rhs: {ms12:.3f} ms per batch")
+    # the same solve once more with the per-category timers (not in the timed region)
+    tt = W.SolverParams.make(tol_outer=tuned.tol_outer, tol_inner=tuned.tol_inner, max_outer=tuned.max_outer,
+                             max_inner=tuned.max_inner, ras=tuned.ras, timers=1)
+    _, st_t = lat.solve_nested(tt, kappa, csw, e, phi)
+    roof_dom, roof_dom_other = domain_kernel_rooflines(torch, W, lat, big, tuned.ras, eta32, kappa, csw, stats[-1])
+    if roof_dom:
+        log(f"domain kernels: {roof_dom['kernel'][:40]} {roof_dom['us_per_launch']} us, "
+            f"{roof_dom['achieved']} TFLOP/s")
+    plain_ms, pst = plain_f64(torch, lat, kappa, csw, e, phi, tol, reps=2)
+    log(f"32^4 plain FP64 {plain_ms:.3f} ms ({pst['outer_iters']} iterations)")
+    headline = {"ms": round(ms_per_step, 3), "ras": ras_desc(tuned), "stats": stats_desc(stats[-1]),
+                "true_resid": true_res, "timers": timers_desc(st_t), "plain_f64_ms": round(plain_ms, 3),
+                "plain_f64_iters": pst["outer_iters"], "speedup_vs_plain_f64": round(plain_ms / ms_per_step, 3)}
+    del e, phi
     lat.close()
 
-    # ---- D-apply against the HBM roofline at 32^4 (1.4 GB FP64 / 705 MB FP32,
-    # larger than the 256 MB Infinity Cache)
-    roof, dapply, big32 = None, {}, None
-    big = (32, 32, 32, 32)
-    if not args.no_dapply or not args.no_extra:
-        big32 = {1.0: I.random_gauge(big, 1.0, 1)}
-    if not args.no_dapply:
+    # ---- 32^4, eps 1.0 (same protocol)
+    c3_eps1 = None
+    if not args.no_extra:
+        U32[1.0] = I.random_gauge(big, 1.0, 1)
         lb = W.Lattice(ctx, big)
-        lb.upload_gauge(big32[1.0])
+        lb.upload_gauge(U32[1.0])
+        e1 = lb.pack(eta32, W.F64)
+        et1 = lb.pack(tune_src32, W.F64)
+        f1 = lb.zeros(W.F64)
+        t1, _ = W.autotune(lb, base16, kappa, csw, et1, 1, storage=W.F16)
+        ms1, st1 = timed_solves(torch, lb, t1, kappa, csw, e1, f1, max(2, args.steps // 2), 1)
+        pl1, pst1 = plain_f64(torch, lb, kappa, csw, e1, f1, tol)
+        c3_eps1 = {"ms": round(ms1, 3), "ras": ras_desc(t1), "stats": stats_desc(st1[-1]),
+                   "plain_f64_ms": round(pl1, 3), "plain_f64_iters": pst1["outer_iters"],
+                   "speedup_vs_plain_f64": round(pl1 / ms1, 3)}
+        del e1, et1, f1
+        lb.close()
+        log(f"32^4 eps=1.0: {ms1:.3f} ms (plain {pl1:.3f} ms)")
+
+    # ================= 16^3 x 32 (eps 0.5): tuned, the literal 8^4 domains, plain FP64, 12 point sources
+    small_dims = (16, 16, 16, 32)
+    c2 = None
+    multi = None
+    anchor4 = None
+    U16 = None
+    if not args.no_small:
+        U16 = I.random_gauge(small_dims, 0.5, 1)
+        l16 = W.Lattice(ctx, small_dims)
+        l16.upload_gauge(U16)
+        eta16 = I.gaussian_source(small_dims, 2)
+        e16 = l16.pack(eta16, W.F64)
+        et16 = l16.pack(I.gaussian_source(small_dims, 7), W.F64)
+        p16 = l16.zeros(W.F64)
+        base = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=100)
+        tuned16, _ = W.autotune(l16, base, kappa, csw, et16, 1)
+        ms16, st16 = timed_solves(torch, l16, tuned16, kappa, csw, e16, p16, args.steps, args.warmup)
+        literal = {}
+        for s in (0, 1):
+            p = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=100,
+                                    ras=W.RasParams.make(block=(8, 8, 8, 8), s=s, n_ras=3, n_dominv=4, storage=W.F32))
+            ms, sts = timed_solves(torch, l16, p, kappa, csw, e16, p16, max(2, args.steps // 2), 1)
+            literal[f"8x8x8x8_s{s}"] = {"ms": round(ms, 3), "stats": stats_desc(sts[-1])}
+            log(f"16^3x32 8^4 s={s}: {ms:.3f} ms")
+        pl16, pst16 = plain_f64(torch, l16, kappa, csw, e16, p16, tol, reps=max(2, args.steps // 2))
+        c2 = {"lattice": list(small_dims), "eps": 0.5, "tuned": {"ms": round(ms16, 3), "ras": ras_desc(tuned16),
+                                                                 "stats": stats_desc(st16[-1])},
+              "literal_8x8x8x8": literal, "plain_f64_ms": round(pl16, 3), "plain_f64_iters": pst16["outer_iters"],
+              "speedup_tuned_vs_plain_f64": round(pl16 / ms16, 3)}
+        log(f"16^3x32 tuned {ms16:.3f} ms, plain FP64 {pl16:.3f} ms")
+        if not args.no_extra:
+            x0, eta12 = I.point_sources(small_dims, 3)
+            e12 = l16.pack(eta12, W.F64, 12)
+            phi12 = l16.zeros(W.F64, 12)
+            tuned12, _ = W.autotune(l16, base, kappa, csw, e12, 12)
+            ms12, st12 = timed_solves(torch, l16, tuned12, kappa, csw, e12, phi12, max(2, args.steps // 2), 1, nrhs=12)
+            p1 = l16.pack(eta12[0], W.F64)
+            f1 = l16.zeros(W.F64)
+            ms1, _ = timed_solves(torch, l16, tuned12, kappa, csw, p1, f1, max(2, args.steps // 2), 1)
+            sol12 = l16.unpack(phi12, W.F64, 12)
+            multi = {"rhs": 12, "source_site": x0, "ms_per_batch": round(ms12, 3),
+                     "solves_per_s": round(12e3 / ms12, 2), "ms_single_point_source_same_params": round(ms1, 3),
+                     "per_rhs_cost_vs_single": round(ms12 / 12 / ms1, 3),
+                     "max_true_resid": st12[-1]["true_resid"], "ras": ras_desc(tuned12),
+                     "stats": stats_desc(st12[-1])}
+            del e12, phi12, p1, f1
+            log(f"12 rhs: {ms12:.3f} ms per batch")
+        del e16, et16, p16
+        l16.close()
+        # the 4^4 plain-method anchor (eps 0.5, kappa 0.12): launch-bound FP64 BiCGStab
+        d4 = (4, 4, 4, 4)
+        l4 = W.Lattice(ctx, d4)
+        l4.upload_gauge(I.random_gauge(d4, 0.5, 1))
+        e4, p4 = l4.pack(I.gaussian_source(d4, 2), W.F64), l4.zeros(W.F64)
+        ms4, st4 = plain_f64(torch, l4, 0.12, 1.0, e4, p4, 1e-10, reps=20)
+        anchor4 = {"lattice": list(d4), "kappa": 0.12, "ms": round(ms4, 3), "iters": st4["outer_iters"],
+                   "true_resid": st4["true_resid"], "us_per_iter": round(ms4 * 1e3 / st4["outer_iters"], 1)}
+        l4.close()
+
+    # ================= D-apply against the HBM roofline at 32^4
+    roof, dapply = None, {}
+    if not args.no_dapply:
+        Ud = U32.get(1.0)
+        if Ud is None:
+            Ud = I.random_gauge(big, 1.0, 1)
+        lb = W.Lattice(ctx, big)
+        lb.upload_gauge(Ud)
         for prec in (1, 2, 0):
             us = time_dapply(torch, I, lb, prec)
             gbs = DAPPLY_BYTES[prec] * lb.V / us / 1e3
@@ -552,81 +686,79 @@ def main():
         dapply["f32_12rhs"] = {"us": round(us12, 2), "GBps": round(gbs12, 1), "frac": round(gbs12 / HBM_PEAK_GBS, 4),
                                "gflops": round(12 * DAPPLY_FLOPS * lb.V / us12 / 1e3, 1),
                                "bytes_per_site": DAPPLY_12RHS_BYTES_F32}
-        V = lb.V
         f32 = dapply["f32"]
-        tb = measured_traffic("dapply_counters.json", DAPPLY_SOURCES, "1", V)
         roof = {"bound": "hbm", "achieved": f32["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": f32["frac"], "traffic": tb,
+                "frac": f32["frac"], "traffic": measured_traffic("dapply_counters.json", DAPPLY_SOURCES, "1", lb.V),
                 "kernel": "k_dslash_xy<F32> full-lattice D-apply, 32^4, 672 algorithmic B/site x 1048576 sites "
                           "per launch", "us_per_launch": f32["us"]}
         lb.close()
         log(f"D-apply 32^4: {dapply}")
 
-    # ---- 32^4, eps in {0.3, 1.0}: FP16-storage RAS, autotuned domain shape
-    c3 = None
-    if not args.no_extra:
-        c3 = {}
-        big32[0.3] = I.random_gauge(big, 0.3, 1)
-        eta32 = I.gaussian_source(big, 2)
-        for eps in (0.3, 1.0):
-            lb = W.Lattice(ctx, big)
-            lb.upload_gauge(big32[eps])
-            e32 = lb.pack(eta32, W.F64)
-            f32v = lb.zeros(W.F64)
-            b16 = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=100,
-                                      ras=W.RasParams.make(block=(4, 4, 4, 4), storage=W.F16))
-            t16, _ = W.autotune(lb, b16, kappa, csw, e32, 1)
-            t16.ras.storage = W.F16
-            ms32, st32 = timed_solves(torch, lb, t16, kappa, csw, e32, f32v, 2, 1)
-            lb.solve_bicgstab_f64(tol, 100000, kappa, csw, e32, f32v)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, pst32 = lb.solve_bicgstab_f64(tol, 100000, kappa, csw, e32, f32v)
-            torch.cuda.synchronize()
-            pl32 = (time.perf_counter() - t0) * 1e3
-            c3[f"eps{eps}"] = {"ms": round(ms32, 3), "ras": ras_desc(t16), "stats": stats_desc(st32[-1]),
-                               "plain_f64_ms": round(pl32, 3), "plain_f64_iters": pst32["outer_iters"],
-                               "speedup_vs_plain_f64": round(pl32 / ms32, 3)}
-            lb.close()
-            log(f"32^4 eps={eps}: {ms32:.3f} ms (plain {pl32:.3f} ms)")
-
     paper = None
     if not args.no_extra and not args.no_paper:
-        paper = paper_table(torch, W, ctx, big, big32[0.3], eta32)
+        paper = paper_table(torch, W, ctx, big, U32[0.3], eta32)
         paper["eps"] = 0.3
         log(f"paper table: {paper}")
-    del big32
 
     serving = None
     if not args.no_extra and not args.no_serve:
         serving = serve_bench(W, I, np, ctx, args.requests, args.slots)
 
-    # ---- CPU baseline: the FP64 oracle's nested RAS solve on the same input and parameters
+    # ================= CPU baseline: the FP64 oracle on the host cores
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import Oracle
-        o = Oracle(dims, U)
+        cores = Oracle.num_threads()
+        # the GPU solutions checked by the oracle's own operator
+        gres32 = oracle_resid(Oracle, np, big, U32[0.3], eta32, sol32, kappa, csw)
+        log(f"oracle: 32^4 GPU solution true residual {gres32:.3e}")
+        o = Oracle(big, U32[0.3])
         r = tuned.ras
+        n_inner = 3
         t0 = time.perf_counter()
-        osol, info = o.nested(eta, kappa, csw, tol=tol, tol_inner=tuned.tol_inner, max_inner=100, ras=True,
-                              block=tuple(r.block), s=r.s, n_ras=r.n_ras, n_dominv=r.n_dominv)
+        _, info = o.nested(eta32, kappa, csw, tol=tol, max_outer=1, tol_inner=tuned.tol_inner, max_inner=n_inner,
+                           ras=True, block=tuple(r.block), s=r.s, n_ras=r.n_ras, n_dominv=r.n_dominv)
         tc = time.perf_counter() - t0
-        # the GPU solution, checked by the oracle's own operator
-        gres = float(np.linalg.norm(eta - o.apply_D(sol, kappa, csw)) / np.linalg.norm(eta))
-        cpu = {"value": round(1.0 / tc, 5), "unit": "solves/s", "cores": Oracle.num_threads(), "kind": "oracle",
-               "sample": f"one complete FP64 nested RAS-BiCGStab solve of the same 16^3x32 system with the same "
-                         f"RAS parameters ({info['outer_iters']} outer / {info['inner_iters']} inner iterations, "
-                         f"{tc:.1f} s)",
-               "gpu_solution_true_resid_by_oracle": gres}
-        log(f"oracle solve {tc:.1f} s")
-        # the 4^4 plain-method anchor on the host, beside the GPU's plain_4x4_f64
-        d4 = (4, 4, 4, 4)
-        o4 = Oracle(d4, I.random_gauge(d4, 0.5, 1))
+        per_inner = tc / max(1, info["inner_iters"])
+        gpu_inner = stats[-1]["inner_iters"]
+        est = per_inner * gpu_inner
+        # the oracle D-apply at all cores (32^4) and at one thread (16^3x32)
         t0 = time.perf_counter()
-        _, inf4 = o4.bicgstab(I.gaussian_source(d4, 2), 0.12, 1.0, tol=1e-10)
-        cpu["plain_4x4_f64"] = {"ms": round((time.perf_counter() - t0) * 1e3, 3), "iters": inf4["iters"]}
+        o.apply_D(eta32, kappa, csw)
+        td_all = time.perf_counter() - t0
+        del o
+        Oracle.set_threads(1)
+        o1 = Oracle(small_dims, U16 if U16 is not None else I.random_gauge(small_dims, 0.5, 1))
+        eta16h = I.gaussian_source(small_dims, 2)
+        t0 = time.perf_counter()
+        o1.apply_D(eta16h, kappa, csw)
+        td_one = time.perf_counter() - t0
+        del o1
+        Oracle.set_threads(cores)
+        V32, V16 = I.volume(big), I.volume(small_dims)
+        cpu = {"value": round(1.0 / est, 5), "unit": "solves/s", "cores": cores, "kind": "oracle",
+               "sample": f"{info['inner_iters']} inner iterations (1 outer) of the FP64 oracle's nested RAS-BiCGStab "
+                         f"solve of the same 32^4 system with the tuned RAS parameters ({tc:.1f} s on {cores} "
+                         f"threads), scaled to the {gpu_inner} inner iterations of the GPU solve",
+               "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+               "gpu_solution_true_resid_by_oracle": gres32,
+               "dapply_f64_32x4_all_cores": {"s": round(td_all, 3), "threads": cores,
+                                             "GBps": round(DAPPLY_BYTES[0] * V32 / td_all / 1e9, 2),
+                                             "gflops": round(DAPPLY_FLOPS * V32 / td_all / 1e9, 2)},
+               "dapply_f64_16x16x16x32_one_thread": {"s": round(td_one, 3), "threads": 1,
+                                                     "GBps": round(DAPPLY_BYTES[0] * V16 / td_one / 1e9, 2),
+                                                     "gflops": round(DAPPLY_FLOPS * V16 / td_one / 1e9, 2)}}
+        if multi is not None:
+            resid = [oracle_resid(Oracle, np, small_dims, U16, eta12[k], sol12[k], kappa, csw) for k in (0, 5, 11)]
+            multi["true_resid_by_oracle_rhs_0_5_11"] = resid
+        if anchor4 is not None:
+            d4 = (4, 4, 4, 4)
+            o4 = Oracle(d4, I.random_gauge(d4, 0.5, 1))
+            t0 = time.perf_counter()
+            _, inf4 = o4.bicgstab(I.gaussian_source(d4, 2), 0.12, 1.0, tol=1e-10)
+            cpu["plain_4x4_f64"] = {"ms": round((time.perf_counter() - t0) * 1e3, 3), "iters": inf4["iters"]}
+        log(f"oracle baseline {cpu['value']} solves/s (sample {tc:.1f} s)")
 
-    st0 = stats[-1]
     out = {
         "metric": METRIC,
         "value": round(1e3 / ms_per_step, 3),
@@ -638,26 +770,30 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64/f32 (outer FP64; inner BiCGStab and RAS arithmetic FP32)",
-        "data": "synthetic (seeded random SU(3) gauge field eps=0.5 and Gaussian source)",
-        "config": {"workload": "16^3x32 nested RAS-BiCGStab solve to 1e-10 (kappa 0.125, c_sw 1.0)",
-                   "lattice": list(dims), "eps": 0.5, "kappa": kappa, "csw": csw, "rhs": 1,
-                   "ras": ras_desc(tuned), "parallelism": "single GPU"},
+        "dtype": "f64/f32/f16 (outer BiCGStab FP64; inner BiCGStab FP32; RAS domain solves in FP32 arithmetic "
+                 "on FP16 storage of links, clover and sweep fields)",
+        "data": "synthetic (seeded random SU(3) gauge field eps=0.3 and Gaussian source)",
+        "config": {"workload": "32^4 nested RAS-BiCGStab solve to 1e-10 (eps 0.3, kappa 0.125, c_sw 1.0; "
+                               "FP16-storage domain solves, domain shape autotuned over 4^4, 4^3x8, 8^4)",
+                   "lattice": list(big), "eps": 0.3, "kappa": kappa, "csw": csw, "rhs": 1, "ras": ras_desc(tuned),
+                   "source_seed": 2, "tuning_source_seed": 7, "parallelism": "single GPU"},
         "time_to_solution_ms": round(ms_per_step, 3),
         "true_residual": true_res,
-        "solve_stats": stats_desc(st0),
+        "solve_stats": stats_desc(stats[-1]),
+        "timers": timers_desc(st_t),
         "autotune_s": round(tune_s, 2),
-        "plain_f64_bicgstab_ms": round(plain_ms, 3),
-        "plain_f64_iters": pst["outer_iters"],
-        "speedup_vs_plain_f64": round(plain_ms / ms_per_step, 3),
-        "literal_8x8x8x8": literal,
-        "plain_4x4_f64": small,
+        "plain_f64_bicgstab_ms": headline["plain_f64_ms"],
+        "plain_f64_iters": headline["plain_f64_iters"],
+        "speedup_vs_plain_f64": headline["speedup_vs_plain_f64"],
+        "solve_32x4_eps1.0_f16": c3_eps1,
+        "solve_16x16x16x32": c2,
         "multi_rhs_12": multi,
-        "solve_32x4_f16": c3,
+        "plain_4x4_f64": anchor4,
         "paper_table1_32x4": paper,
         "dapply_32x4": dapply,
         "serving": serving,
         "roofline": roof_dom,
+        "roofline_other_domain_kernel": roof_dom_other,
         "roofline_dapply": roof,
         "cpu_baseline": cpu,
     }

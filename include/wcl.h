@@ -73,20 +73,39 @@ typedef struct wcl_ctx wcl_ctx;
 typedef struct wcl_lattice wcl_lattice;
 typedef struct wcl_server wcl_server;
 
+/* ---- domain solvers (Sec. 2: "a fixed iteration solver with N_dominv
+ * iterations"; every reading runs exactly n_dominv iterations from zero) ---- */
+#define WCL_DOMSOLVE_MR 0        /* minimal residual: q = D rho, alpha = <q,rho>/<q,q> */
+#define WCL_DOMSOLVE_JACOBI 1    /* block Jacobi: x <- x + A^-1 (b - D x), A = the site (clover) term */
+#define WCL_DOMSOLVE_BICGSTAB 2  /* truncated BiCGStab (no restarts, no early exit) */
+
+/* ---- Schwarz iterations (Sec. 1-2) ---- */
+#define WCL_SCHWARZ_RAS 0   /* restricted additive Schwarz, Algorithm 1 */
+#define WCL_SCHWARZ_AS 1    /* additive Schwarz: the whole extended solutions are summed (overlaps add up),
+                               refined by the Richardson iteration phi += v, r -= D v */
+#define WCL_SCHWARZ_SAP 2   /* multiplicative Schwarz (Schwarz alternating procedure): the domains are
+                               coloured by the parity of their block coordinates; each sweep solves the
+                               colour-0 domains, updates r, then the colour-1 domains, updates r */
+
 /* RAS parameters (Sec. 2): domains Omega_i are the tiling of the lattice by
  * `block` from the origin; Omega'_i grows each domain by s sites per side in
  * every direction it does not span (overlap depth d = 2s, Sec. 4).
  * n_ras sweeps of Algorithm 1, each domain solved approximately by n_dominv
- * minimal-residual steps from zero (the paper's fixed-iteration domain
- * solver).  storage = WCL_F32 or WCL_F16 for the gauge/clover fields and the
- * sweep-internal residual/correction fields. */
+ * iterations of the domain solver from zero (the paper's fixed-iteration
+ * domain solver; minimal residual by default).  storage = WCL_F32 or WCL_F16
+ * for the gauge/clover fields and the sweep-internal residual/correction
+ * fields.  block_solver and schwarz select the variants above (0 = the
+ * defaults: MR domain solves inside RAS); the Jacobi and BiCGStab domain
+ * solvers and the AS and SAP iterations run on the split path. */
 typedef struct wcl_ras_params {
     int block[4];
     int s;
     int n_ras;
     int n_dominv;
     int storage;
-    int kernel;     /* WCL_BLOCK_* */
+    int kernel;        /* WCL_BLOCK_* */
+    int block_solver;  /* WCL_DOMSOLVE_* */
+    int schwarz;       /* WCL_SCHWARZ_* */
 } wcl_ras_params;
 
 #define WCL_PRECOND_NONE 0
@@ -106,22 +125,33 @@ typedef struct wcl_solver_params {
     int max_restarts;
     int precond;            /* WCL_PRECOND_* */
     wcl_ras_params ras;
+    int even_odd;           /* 1: solve the even-odd reduced system (precond must be NONE); 0: the full D */
+    int timers;             /* 1: per-category HIP-event times into wcl_solve_stats (ms_dslash, ...) */
 } wcl_solver_params;
 
 /* Per-solve statistics.  The counters follow the paper's timing chart
  * (Sec. 4/5): dslash_full is its "Dv operation count", dslash_block and
  * ras_sweeps measure the domain inversion work; ms_total is the HIP-event
- * time of the whole solve on its stream. */
+ * time of the whole solve on its stream.  With wcl_solver_params.timers = 1
+ * the solve's stream time is split by HIP events into the chart's compute
+ * categories: ms_dslash = full-lattice D applications of every precision
+ * (T_Dv^calc; with even_odd, the reduced operator), ms_dominv = the domain
+ * solver launches of the Schwarz sweeps, including the residual update
+ * r -= D v that the on-chip path forms inside the next sweep (T_dominv^calc),
+ * ms_blas = BLAS-1 updates, reductions and precision conversions of both
+ * solver levels, ms_host = device idle while the host reads the scalars and
+ * decides (one wait per iteration).  The four add up to ms_total. */
 typedef struct wcl_solve_stats {
     int outer_iters;
     int inner_iters;        /* summed over all inner solves */
     int restarts;           /* true-residual restarts + breakdown restarts */
     int converged;
     int64_t dslash_full;    /* full-lattice D applications (all precisions) */
-    int64_t dslash_block;   /* domain-solver MR steps (each = one D_Omega' over all domains) */
+    int64_t dslash_block;   /* domain-solver iterations (each = one D_Omega' over all domains) */
     int64_t ras_sweeps;
     double true_resid;      /* |eta - D phi| / |eta| in FP64 at exit */
     double ms_total;
+    double ms_dslash, ms_dominv, ms_blas, ms_host;   /* only with timers = 1, else 0 */
 } wcl_solve_stats;
 
 /* ---- context and lattice ---- */
@@ -212,16 +242,20 @@ int wcl_solve_bicgstab_f64(wcl_lattice* lat, double tol, int max_iter, double ka
  * depth, N_dominv, NRAS; Sec. 5 scans them by hand) plus the domain shape,
  * storage precision, inner tolerance and the D-apply's lanes per site, by
  * timing complete nested solves of eta on this lattice: stage 1 scans
- * domain shape {4^4, 4^3x8, 8^4} x overlap {0, 1} x storage {FP32, FP16};
- * stage 2 scans N_dominv {2, 3, 4, 5, 6} x NRAS {1, 2, 3, 4}; stage 3 the inner
- * tolerance {1e-2, 1e-3, 1e-4, 1e-5} and lanes per site {1, 2}.  Candidates that
- * do not converge are skipped.  With cache_path != NULL the result is read
+ * domain shape {4^4, 4^3x8, 8^4} x overlap {0, 1} x storage (bit 0 of
+ * storage_mask: FP32, bit 1: FP16; 0 = both); stage 2 scans N_dominv
+ * {2, 3, 4, 5, 6} x NRAS {1, 2, 3, 4}; stage 3 the inner tolerance
+ * {1e-2, 1e-3, 1e-4, 1e-5} and lanes per site {1, 2}.  Candidates that do not
+ * converge are skipped.  eta is a tuning source: the chosen parameters serve
+ * any source on this lattice.  With cache_path != NULL the result is read
  * from / appended to that JSON-lines file, keyed by device architecture,
- * dims, nrhs, kappa and c_sw.  *best receives the chosen parameters (tol_outer,
- * max_* and max_restarts are copied from *base), *best_ms its solve time;
- * the lattice keeps the chosen lanes per site.  Blocks until done. */
+ * dims, nrhs, kappa, c_sw and storage_mask.  *best receives the chosen
+ * parameters (tol_outer, max_* and max_restarts are copied from *base;
+ * MR domain solves inside RAS, full D), *best_ms its solve time; the lattice
+ * keeps the chosen lanes per site.  Blocks until done. */
 int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, double kappa, double csw, const void* eta_dev,
-                 int nrhs, const char* cache_path, wcl_solver_params* best, double* best_ms, void* stream);
+                 int nrhs, int storage_mask, const char* cache_path, wcl_solver_params* best, double* best_ms,
+                 void* stream);
 
 /* ---- serving (continuous batching of solve requests) ----
  * A server owns resident gauge/clover fields per registered configuration and

@@ -572,6 +572,16 @@ int oracle_num_threads() {
 #endif
 }
 
+// Number of OpenMP threads for the following calls (timing at 1 thread and at
+// all cores).
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 // gamma matrices [4][4][4] complex and sigma [4][4][4][4] complex, for tests.
 void oracle_gammas(double* g, double* sigma) {
     std::memcpy(g, DIRAC.g, sizeof(DIRAC.g));

@@ -105,7 +105,7 @@ uint64_t wcl_bytes_in_use(wcl_ctx* ctx) { return ctx ? ctx->in_use : 0; }
 // in x and y and 8 in z.  Whole x rows keep the x-neighbours of a t-slice
 // inside the column (the hops that leave a column are the ones re-fetched
 // from memory most often); measured on 32^4 this cross-section beat 16x16x8,
-// 8x8x4 and 32x32x32.  WCL_COLUMN ("cx,cy,cz") overrides the caps.
+// 8x8x4 and 32x32x32.
 static int pow2_divisor(int L, int cap) {
     int c = 1;
     while (c * 2 <= cap && L % (c * 2) == 0) c *= 2;
@@ -138,15 +138,7 @@ int wcl_create_lattice(wcl_ctx* ctx, const int dims[4], const int bc[4], wcl_lat
     lat->ctx = ctx;
     lat->V = V;
     Geom& g = lat->g;
-    int caps[3] = {32, 32, 8};
-    if (const char* e = getenv("WCL_COLUMN")) {   // "cx,cy,cz" caps, for layout experiments
-        int c0, c1, c2;
-        if (sscanf(e, "%d,%d,%d", &c0, &c1, &c2) == 3 && c0 > 0 && c1 > 0 && c2 > 0) {
-            caps[0] = c0;
-            caps[1] = c1;
-            caps[2] = c2;
-        }
-    }
+    const int caps[3] = {32, 32, 8};
     for (int mu = 0; mu < 4; ++mu) {
         g.L[mu] = dims[mu];
         g.bc[mu] = bc ? bc[mu] : 1;
@@ -162,12 +154,8 @@ int wcl_create_lattice(wcl_ctx* ctx, const int dims[4], const int bc[4], wcl_lat
     g.Vc = g.S * dims[3];
     g.V = (int)V;
     // lanes per site of the D-apply (1, 2 or 4); one lane per site measured
-    // fastest on 16^3x32 and 32^4; WCL_DSLASH_LPS overrides it
+    // fastest on 16^3x32 and 32^4; the autotuner may pick another
     lat->lps = 1;
-    if (const char* e = getenv("WCL_DSLASH_LPS")) {
-        int v = atoi(e);
-        if (v == 1 || v == 2 || v == 4) lat->lps = v;
-    }
     *out = lat;
     return WCL_OK;
 }

@@ -420,15 +420,6 @@ __global__ __launch_bounds__(256) void k_dslash_ml(DslashArgs a) {
     }
 }
 
-// WCL_DSLASH_XY=0 keeps every launch on the neighbour-load kernel (A/B runs)
-static bool dslash_xy_enabled() {
-    static const bool on = [] {
-        const char* e = getenv("WCL_DSLASH_XY");
-        return !(e && e[0] == '0');
-    }();
-    return on;
-}
-
 static size_t dslash_launch_bytes(int V, int gp, int spi, int spo) {
     return gauge_bytes(gp, V) + clover_bytes(gp, V) + spinor_rhs_bytes(spi, V) + spinor_rhs_bytes(spo, V);
 }
@@ -443,7 +434,7 @@ static int launch_t(const DslashArgs& a, hipStream_t st) {
             // non-temporal field loads only for one rhs streaming more than the
             // 256 MB Infinity Cache holds
             const bool nt = a.nrhs == 1 && dslash_launch_bytes(a.g.V, GP, SPI, SPO) > (256u << 20);
-            if (dslash_xy_enabled() && dslash_xy_layout(a.g)) {
+            if (dslash_xy_layout(a.g)) {
                 if (nt) k_dslash_xy<GP, SPI, SPO, EPI, SPY, true><<<tiles * a.nrhs, 256, 0, st>>>(a);
                 else k_dslash_xy<GP, SPI, SPO, EPI, SPY, false><<<tiles * a.nrhs, 256, 0, st>>>(a);
             } else if (nt) {

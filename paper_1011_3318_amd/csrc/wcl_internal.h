@@ -102,6 +102,8 @@ struct Blocks {
     int nblocks;
     int ev;  // extended volume
     int n_ras, n_dominv;
+    int solver;    // WCL_DOMSOLVE_*
+    int schwarz;   // WCL_SCHWARZ_*
 };
 
 // ------------------------------------------------------ storage -------

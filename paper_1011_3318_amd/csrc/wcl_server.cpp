@@ -5,8 +5,9 @@
 // its solve needs fits the budget; then the slot's worker thread runs it on
 // the slot's own HIP stream with the slot's own workspace, so admitted
 // requests overlap on the device.  A slot keeps its workspace between
-// requests (no device allocation on the hot path once warm); the admission
-// test charges a request only for the growth of that workspace.
+// requests (no device allocation on the hot path once warm); admission
+// (admit_decide in wcl_admit.h) reuses it for a request of the same lattice
+// and parameters and otherwise releases it and charges the request in full.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -17,6 +18,7 @@
 #include <thread>
 #include <vector>
 
+#include "wcl_admit.h"
 #include "wcl_kernels.h"
 
 namespace {
@@ -32,9 +34,27 @@ struct Job {
     wcl_solver_params params{};
     wcl_lattice* lat = nullptr;
     size_t need = 0;       // estimated workspace bytes of the solve
-    size_t reserved = 0;   // growth charged at admission
+    size_t reserved = 0;   // bytes charged at admission
+    uint64_t key = 0;      // lattice and solver parameters the workspace is built for
     double t_submit = 0, t_admit = 0;
 };
+
+// FNV-1a over the lattice handle and every parameter that sizes the workspace
+uint64_t job_key(const wcl_lattice* lat, const wcl_solver_params& p) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (v >> (8 * k)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    mix((uint64_t)(uintptr_t)lat);
+    const int f[] = {p.precond, p.even_odd, p.ras.block[0], p.ras.block[1], p.ras.block[2], p.ras.block[3],
+                     p.ras.s, p.ras.n_ras, p.ras.n_dominv, p.ras.storage, p.ras.kernel, p.ras.block_solver,
+                     p.ras.schwarz};
+    for (int v : f) mix((uint64_t)(uint32_t)v);
+    return h | 1;   // never 0
+}
 
 // default RAS domain: 4 in every direction it divides, else 2, else the extent
 int default_block(int L) { return L % 4 == 0 ? 4 : (L % 2 == 0 ? 2 : L); }
@@ -54,6 +74,7 @@ struct wcl_server {
         hipStream_t st = nullptr;
         Workspace* ws = nullptr;
         size_t held = 0;    // bytes the slot's workspace holds
+        uint64_t key = 0;   // what that workspace was built for
         bool busy = false;
         Job job;
         std::condition_variable cv;
@@ -77,27 +98,33 @@ struct wcl_server {
         return b;
     }
 
+    void release_workspace(Slot* s) {
+        wcl_workspace_delete(s->ws);
+        s->ws = wcl_workspace_new(ctx);
+        s->held = 0;
+        s->key = 0;
+    }
+
     // Admits queued requests in FIFO order while a slot is free and the
-    // budget allows.  Called with mu held.
+    // budget allows (admit_decide).  Called with mu held.
     void admit() {
         while (!queue.empty()) {
-            Slot* free_slot = nullptr;
-            for (auto* s : slots)
-                if (!s->busy) {
-                    // prefer the free slot whose workspace already fits
-                    if (!free_slot || (s->held >= queue.front().need && free_slot->held < queue.front().need))
-                        free_slot = s;
-                }
-            if (!free_slot) return;
+            std::vector<AdmitSlot> st;
+            for (auto* s : slots) st.push_back(AdmitSlot{s->busy, s->held, s->key});
             Job& j = queue.front();
-            const size_t growth = j.need > free_slot->held ? j.need - free_slot->held : 0;
-            const size_t used = resident_bytes() + held_bytes() + reserved;
-            if (used + growth > budget) return;   // head of line waits for memory
+            const AdmitDecision d = admit_decide(st, budget, resident_bytes(), reserved, j.need, j.key);
+            if (d.slot < 0) return;   // head of line waits for a slot or for memory
+            Slot* free_slot = slots[d.slot];
+            if (d.release_idle)
+                for (auto* s : slots)
+                    if (!s->busy && s != free_slot && s->held) release_workspace(s);
+            if (d.release_slot) release_workspace(free_slot);
             Job job = j;
             queue.pop_front();
-            job.reserved = growth;
+            job.reserved = d.charge;
             job.t_admit = now_s();
-            reserved += growth;
+            reserved += d.charge;
+            free_slot->key = job.key;
             free_slot->job = job;
             free_slot->busy = true;
             free_slot->cv.notify_one();
@@ -276,6 +303,7 @@ int wcl_submit(wcl_server* srv, const wcl_request* req, uint64_t* ticket) {
     }
     j.need = nested_workspace_bytes(j.lat, &j.params, 1) + 2 * spinor_rhs_bytes(WCL_F64, j.lat->V) +
              (size_t)j.lat->V * 24 * sizeof(double);
+    j.key = job_key(j.lat, j.params);
     if (srv->resident_bytes() + j.need > srv->budget) {
         wcl_set_error("wcl_submit: request needs %llu bytes, more than the budget leaves",
                       (unsigned long long)j.need);

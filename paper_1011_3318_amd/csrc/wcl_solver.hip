@@ -17,9 +17,62 @@
 
 #include "wcl_kernels.h"
 
+// ------------------------------------------------------------ timeline --
+// Per-category device time of one solve (the paper's timing chart, Sec. 4):
+// an event is recorded on the solve's stream whenever the category of the
+// enqueued work changes; after the solve the interval from each mark to the
+// next is added to the category of the mark.  Off unless requested.
+enum { CAT_DSLASH = 0, CAT_DOMINV = 1, CAT_BLAS = 2, CAT_HOST = 3, CAT_N = 4 };
+struct Timeline {
+    bool on = false;
+    hipStream_t st = nullptr;
+    std::vector<hipEvent_t> pool;
+    std::vector<int> cats;
+    int cur = -1;
+    void start(hipStream_t s) {
+        on = true;
+        st = s;
+        cats.clear();
+        cur = -1;
+    }
+    void mark(int cat) {
+        if (!on || cat == cur) return;
+        const size_t k = cats.size();
+        if (k == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                on = false;
+                return;
+            }
+            pool.push_back(e);
+        }
+        if (hipEventRecord(pool[k], st) != hipSuccess) {
+            on = false;
+            return;
+        }
+        cats.push_back(cat);
+        cur = cat;
+    }
+    // end: an event recorded after the last work of the solve, completed
+    void finish(hipEvent_t end, double ms[CAT_N]) {
+        for (int c = 0; c < CAT_N; ++c) ms[c] = 0.0;
+        if (!on) return;
+        for (size_t k = 0; k < cats.size(); ++k) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, pool[k], k + 1 < cats.size() ? pool[k + 1] : end) == hipSuccess)
+                ms[cats[k]] += t;
+        }
+        on = false;
+    }
+    ~Timeline() {
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
 // ----------------------------------------------------------- workspace --
 struct Workspace {
     wcl_ctx* ctx = nullptr;
+    Timeline tl;
     struct Item {
         std::string name;
         void* p;
@@ -130,7 +183,8 @@ int make_blocks(const wcl_lattice* lat, const wcl_ras_params* p, Blocks* B) {
         return WCL_EINVAL;
     }
     if (p->s < 0 || p->n_ras < 1 || p->n_dominv < 1 || (p->storage != WCL_F32 && p->storage != WCL_F16) ||
-        p->kernel < 0 || p->kernel > 2) {
+        p->kernel < 0 || p->kernel > 2 || p->block_solver < 0 || p->block_solver > 2 || p->schwarz < 0 ||
+        p->schwarz > 2) {
         wcl_set_error("RAS parameters invalid (s=%d n_ras=%d n_dominv=%d storage=%d kernel=%d)", p->s, p->n_ras,
                       p->n_dominv, p->storage, p->kernel);
         return WCL_EINVAL;
@@ -160,6 +214,8 @@ int make_blocks(const wcl_lattice* lat, const wcl_ras_params* p, Blocks* B) {
     }
     B->n_ras = p->n_ras;
     B->n_dominv = p->n_dominv;
+    B->solver = p->block_solver;
+    B->schwarz = p->schwarz;
     return WCL_OK;
 }
 
@@ -226,6 +282,7 @@ static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int stora
     }
     for (int j = 0; j < B.n_ras; ++j) {
         const bool last = j == B.n_ras - 1;
+        ws->tl.mark(CAT_DOMINV);
         a.accumulate = j > 0;
         a.vj_stride = sst;
         // projection r_{Omega'} = P r, then N_dominv MR steps, then R + sum
@@ -283,6 +340,7 @@ static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int stora
             d.nrhs = nrhs;
             d.lps = lat->lps;
             d.sc = sc;
+            ws->tl.mark(CAT_DSLASH);
             WCL_CHECK(launch_dslash(d, storage, storage, storage, DS_AXPY, src_prec, st));
             if (stats) stats->dslash_full += nrhs;
         }
@@ -303,6 +361,7 @@ struct EngineResult {
     int iters = 0;
     int restarts = 0;
     bool converged = false;
+    bool breakdown = false;    // some rhs was dropped for a persistent breakdown
     double true_resid = 0.0;   // max over rhs (only with true_check)
 };
 
@@ -372,6 +431,7 @@ struct Engine {
         x.partial = partial;
         x.sc = d;
         if (stats) stats->dslash_full += nrhs;
+        ws->tl.mark(CAT_DSLASH);
         return launch_dslash(x, gp, P, P, DS_DOT, P, st);
     }
     // out = b - D x (FP64 true residual)
@@ -389,15 +449,18 @@ struct Engine {
         a.nrhs = nrhs;
         a.lps = lat->lps;
         if (stats) stats->dslash_full += nrhs;
+        ws->tl.mark(CAT_DSLASH);
         return launch_dslash(a, gp, P, P, DS_AXPY, P, st);
     }
     // The finalize kernel before every pull has written the active rhs'
     // scalars into h already; inactive rhs do not change on the device.
     int pull() {
+        ws->tl.mark(CAT_HOST);
         WCL_HIP(hipStreamSynchronize(st));
         return WCL_OK;
     }
     int push() {
+        ws->tl.mark(CAT_HOST);
         WCL_HIP(hipMemcpyAsync(d, h, sizeof(Scal) * nrhs, hipMemcpyHostToDevice, st));
         WCL_HIP(hipStreamSynchronize(st));
         return WCL_OK;
@@ -417,10 +480,13 @@ struct Engine {
             h[i] = z;
         }
         WCL_CHECK(push());
+        ws->tl.mark(CAT_BLAS);
         WCL_CHECK(blas_init(P, V, nrhs, d, b, x, r, rh, p, v, partial, st));
         WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RHO, st, hmap));
         WCL_CHECK(pull());
         std::vector<double> bnorm(nrhs, 0.0), rh2(nrhs, 0.0);
+        // rhs dropped for a persistent breakdown (reported as WCL_EBREAKDOWN)
+        std::vector<int> broke(nrhs, 0);
         std::vector<int> conv(nrhs, 0), restarts(nrhs, 0);
         // |b - D x| / |b| of the rhs whose convergence a true residual
         // confirmed (x does not change afterwards); -1 = not known
@@ -455,6 +521,7 @@ struct Engine {
         bool p_ready = false;
         while (any_active() && it < max_iter) {
             ++it;
+            ws->tl.mark(CAT_BLAS);
             if (!p_ready) WCL_CHECK(blas_p_update(P, V, nrhs, d, r, p, v, st));
             p_ready = false;
             std::vector<int> a_now(nrhs);
@@ -462,9 +529,11 @@ struct Engine {
             if (K) WCL_CHECK((*K)(p, ph, d, a_now));
             WCL_CHECK(apply_dot(ph, v, rh));
             // alpha and omega are formed inside the updates that use them
+            ws->tl.mark(CAT_BLAS);
             WCL_CHECK(blas_s_update_fin(P, V, nrhs, d, partial, Gd, r, v, s, st));
             if (K) WCL_CHECK((*K)(s, sh, d, a_now));
             WCL_CHECK(apply_dot(sh, t, s));
+            ws->tl.mark(CAT_BLAS);
             WCL_CHECK(blas_xr_update_fin(P, V, nrhs, d, partial, Gd, x, ph, sh, s, t, r, rh, partial2, st));
             WCL_CHECK(blas_finalize(partial2, Gb, nrhs, d, FIN_RHO, st, hmap));
             WCL_HIP(hipEventRecord(ev, st));
@@ -472,15 +541,16 @@ struct Engine {
                 WCL_CHECK(blas_p_update(P, V, nrhs, d, r, p, v, st));
                 p_ready = true;
             }
+            ws->tl.mark(CAT_HOST);
             WCL_HIP(hipEventSynchronize(ev));
-            bool changed = false, want_true = false;
+            bool changed = false, want_true = false, dropped = false;
             std::vector<int> restart(nrhs, 0);
             for (int i = 0; i < nrhs; ++i) {
                 if (!h[i].active) continue;
                 const double rr = h[i].rr;
                 if (!std::isfinite(rr)) {
                     h[i].active = 0;
-                    changed = true;
+                    changed = dropped = true;
                     continue;
                 }
                 const double rel = std::sqrt(rr) / bnorm[i];
@@ -500,10 +570,17 @@ struct Engine {
                     if (bd) restart[i] = 1;
                 }
             }
+            // A dropped rhs must be inactive on the device before any later
+            // finalize copies the device scalars back into the host mirror.
+            if (dropped) {
+                WCL_CHECK(push());
+                changed = false;
+            }
             const void* restart_src = nullptr;
             if (want_true) {
                 // true residual in the engine's precision: t = b - D x
                 WCL_CHECK(residual(b, x, t));
+                ws->tl.mark(CAT_BLAS);
                 WCL_CHECK(blas_dot(P, V, nrhs, d, t, t, partial, st));
                 WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RR, st, hmap));
                 WCL_CHECK(pull());
@@ -531,6 +608,7 @@ struct Engine {
                 if (restart[i] == 1 || restart[i] == 2) {
                     if (restart[i] == 1 && restarts[i] >= max_restarts + 50) {
                         h[i].active = 0;   // persistent breakdown
+                        broke[i] = 1;
                         changed = true;
                         continue;
                     }
@@ -551,10 +629,12 @@ struct Engine {
                     }
                     if (!any) continue;
                     WCL_CHECK(push());
+                    ws->tl.mark(CAT_BLAS);
                     WCL_CHECK(blas_restart(P, V, nrhs, d, kind == 2 ? restart_src : nullptr, r, rh, p, v, st));
                 }
                 for (int i = 0; i < nrhs; ++i) h[i].breakdown = 0;
                 WCL_CHECK(push());
+                ws->tl.mark(CAT_BLAS);
                 WCL_CHECK(blas_dot(P, V, nrhs, d, rh, r, partial, st));
                 WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RHO, st, hmap));
                 WCL_CHECK(pull());
@@ -571,8 +651,10 @@ struct Engine {
         res->iters = it;
         res->restarts = total_restarts;
         res->converged = true;
+        res->breakdown = false;
         for (int i = 0; i < nrhs; ++i) {
             if (act[i] && !conv[i]) res->converged = false;
+            if (broke[i]) res->breakdown = true;
             act[i] = conv[i];
         }
         if (true_check) {
@@ -586,6 +668,7 @@ struct Engine {
             if (any) {
                 WCL_CHECK(push());
                 WCL_CHECK(residual(b, x, t));
+                ws->tl.mark(CAT_BLAS);
                 WCL_CHECK(blas_dot(P, V, nrhs, d, t, t, partial, st));
                 WCL_CHECK(blas_finalize(partial, Gb, nrhs, d, FIN_RR, st, hmap));
                 WCL_CHECK(pull());
@@ -602,8 +685,13 @@ struct Engine {
 
 static int check_solver_params(const wcl_solver_params* p) {
     if (!p || !(p->tol_outer > 0) || !(p->tol_inner > 0) || p->max_outer < 1 || p->max_inner < 1 ||
-        p->max_restarts < 0 || (p->precond != WCL_PRECOND_NONE && p->precond != WCL_PRECOND_RAS)) {
+        p->max_restarts < 0 || (p->precond != WCL_PRECOND_NONE && p->precond != WCL_PRECOND_RAS) ||
+        (p->even_odd != 0 && p->even_odd != 1) || (p->timers != 0 && p->timers != 1)) {
         wcl_set_error("invalid solver parameters");
+        return WCL_EINVAL;
+    }
+    if (p->even_odd && p->precond != WCL_PRECOND_NONE) {
+        wcl_set_error("the even-odd reduced system is solved without the Schwarz preconditioner (precond = NONE)");
         return WCL_EINVAL;
     }
     return WCL_OK;
@@ -630,6 +718,11 @@ int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, 
     WCL_HIP(hipEventCreate(&e0));
     WCL_HIP(hipEventCreate(&e1));
     WCL_HIP(hipEventRecord(e0, st));
+    ws->tl.on = false;
+    if (prm->timers) {
+        ws->tl.start(st);
+        ws->tl.mark(CAT_HOST);
+    }
 
     Engine inner{lat, ws, "in", WCL_F32, WCL_F32, nrhs, kappa, csw, st, S};
     void *b32 = nullptr, *y32 = nullptr;
@@ -643,6 +736,7 @@ int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, 
     int outer_partials_G = blas_partials(WCL_F64, lat->V);
     Precond Kinner = [&](const void* in, void* out, Scal* sc, const std::vector<int>& act) -> int {
         // b = in/|in| in FP32, inner solve, out = |in| y in FP64
+        ws->tl.mark(CAT_BLAS);
         WCL_CHECK(blas_dot(WCL_F64, lat->V, nrhs, sc, in, in, outer.partial, st));
         WCL_CHECK(blas_finalize(outer.partial, outer_partials_G, nrhs, sc, FIN_PP, st));
         WCL_CHECK(blas_to_f32_scaled(lat->V, nrhs, sc, in, b32, st));
@@ -650,6 +744,7 @@ int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, 
         EngineResult r;
         WCL_CHECK(inner.run(b32, y32, prm->tol_inner, prm->max_inner, use_ras ? &Kras : nullptr, a, false, 0, &r));
         S->inner_iters += r.iters;
+        ws->tl.mark(CAT_BLAS);
         WCL_CHECK(blas_to_f64_scaled(lat->V, nrhs, sc, y32, out, st));
         return WCL_OK;
     };
@@ -660,6 +755,8 @@ int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, 
     WCL_HIP(hipEventSynchronize(e1));
     float ms = 0;
     WCL_HIP(hipEventElapsedTime(&ms, e0, e1));
+    double cat[CAT_N];
+    ws->tl.finish(e1, cat);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != WCL_OK) return rc;
@@ -668,8 +765,17 @@ int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, 
     S->converged = res.converged;
     S->true_resid = res.true_resid;
     S->ms_total = ms;
+    S->ms_dslash = cat[CAT_DSLASH];
+    S->ms_dominv = cat[CAT_DOMINV];
+    S->ms_blas = cat[CAT_BLAS];
+    S->ms_host = cat[CAT_HOST];
     if (!res.converged || !(res.true_resid <= prm->tol_outer)) {
         S->converged = 0;
+        if (res.breakdown) {
+            wcl_set_error("nested BiCGStab: breakdown persisted after %d restarts (true residual %.3e)",
+                          res.restarts, res.true_resid);
+            return WCL_EBREAKDOWN;
+        }
         wcl_set_error("nested BiCGStab: true residual %.3e above tolerance %.3e after %d outer iterations",
                       res.true_resid, prm->tol_outer, res.iters);
         return WCL_ENOTCONV;
@@ -800,6 +906,10 @@ int wcl_solve_bicgstab_f64(wcl_lattice* lat, double tol, int max_iter, double ka
     S->converged = res.converged;
     S->ms_total = ms;
     if (!res.converged) {
+        if (res.breakdown) {
+            wcl_set_error("BiCGStab FP64: breakdown persisted after %d restarts", res.restarts);
+            return WCL_EBREAKDOWN;
+        }
         wcl_set_error("BiCGStab FP64: not converged after %d iterations", res.iters);
         return WCL_ENOTCONV;
     }

@@ -18,15 +18,16 @@ struct Cand {
     int lps;
 };
 
-std::string tune_key(const wcl_lattice* lat, int nrhs, double kappa, double csw) {
+std::string tune_key(const wcl_lattice* lat, int nrhs, double kappa, double csw, int storage_mask) {
     hipDeviceProp_t prop;
     std::string arch = "unknown";
     if (hipGetDeviceProperties(&prop, lat->ctx->device) == hipSuccess) arch = prop.gcnArchName;
     const size_t colon = arch.find(':');
     if (colon != std::string::npos) arch = arch.substr(0, colon);
     char buf[256];
-    snprintf(buf, sizeof buf, "%s|%dx%dx%dx%d|bc%d%d%d%d|nrhs%d|k%.6f|c%.6f", arch.c_str(), lat->g.L[0], lat->g.L[1],
-             lat->g.L[2], lat->g.L[3], lat->g.bc[0], lat->g.bc[1], lat->g.bc[2], lat->g.bc[3], nrhs, kappa, csw);
+    snprintf(buf, sizeof buf, "%s|%dx%dx%dx%d|bc%d%d%d%d|nrhs%d|k%.6f|c%.6f|st%d", arch.c_str(), lat->g.L[0],
+             lat->g.L[1], lat->g.L[2], lat->g.L[3], lat->g.bc[0], lat->g.bc[1], lat->g.bc[2], lat->g.bc[3], nrhs, kappa,
+             csw, storage_mask);
     return buf;
 }
 
@@ -78,23 +79,29 @@ void cache_store(const char* path, const std::string& key, const Cand& c, double
 }  // namespace
 
 extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, double kappa, double csw,
-                            const void* eta_dev, int nrhs, const char* cache_path, wcl_solver_params* best,
-                            double* best_ms, void* stream) {
-    if (!lat || !base || !eta_dev || nrhs < 1 || !best) {
+                            const void* eta_dev, int nrhs, int storage_mask, const char* cache_path,
+                            wcl_solver_params* best, double* best_ms, void* stream) {
+    if (!lat || !base || !eta_dev || nrhs < 1 || !best || storage_mask < 0 || storage_mask > 3) {
         wcl_set_error("wcl_autotune: bad argument");
         return WCL_EINVAL;
     }
+    if (storage_mask == 0) storage_mask = 3;
     WCL_HIP(hipSetDevice(lat->ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    const std::string key = tune_key(lat, nrhs, kappa, csw);
+    const std::string key = tune_key(lat, nrhs, kappa, csw, storage_mask);
     Cand cur{*base, lat->lps};
     cur.p.precond = WCL_PRECOND_RAS;
+    cur.p.even_odd = 0;
+    cur.p.timers = 0;
+    cur.p.ras.block_solver = WCL_DOMSOLVE_MR;
+    cur.p.ras.schwarz = WCL_SCHWARZ_RAS;
     double cur_ms = 0;
     if (cache_path && cache_lookup(cache_path, key, &cur, &cur_ms)) {
         Blocks B;
         if (make_blocks(lat, &cur.p.ras, &B) == WCL_OK) {
             wcl_solver_params out = *base;
             out.precond = WCL_PRECOND_RAS;
+            out.even_odd = 0;
             out.ras = cur.p.ras;
             out.tol_inner = cur.p.tol_inner;
             *best = out;
@@ -143,6 +150,7 @@ extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, dou
     for (const auto& sh : shapes)
         for (int s = 0; s <= 1; ++s)
             for (int storage : {WCL_F32, WCL_F16}) {
+                if (!(storage_mask & (storage == WCL_F32 ? 1 : 2))) continue;
                 Cand c = cur;
                 for (int mu = 0; mu < 4; ++mu) c.p.ras.block[mu] = sh[mu];
                 c.p.ras.s = s;
@@ -182,6 +190,7 @@ extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, dou
     wcl_workspace_delete(ws);
     wcl_solver_params out = *base;
     out.precond = WCL_PRECOND_RAS;
+    out.even_odd = 0;
     out.ras = bestc.p.ras;
     out.tol_inner = bestc.p.tol_inner;
     *best = out;

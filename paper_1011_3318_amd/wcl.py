@@ -14,11 +14,12 @@ import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime libwcl.so links against)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# WCL_LIBRARY names another build of the same library (e.g. to compare kernel variants)
-LIB_PATH = os.environ.get("WCL_LIBRARY") or os.path.join(_HERE, "libwcl.so")
+LIB_PATH = os.path.join(_HERE, "libwcl.so")
 
 F64, F32, F16 = 0, 1, 2
 BLOCK_AUTO, BLOCK_FUSED, BLOCK_SPLIT = 0, 1, 2
+DOMSOLVE_MR, DOMSOLVE_JACOBI, DOMSOLVE_BICGSTAB = 0, 1, 2
+SCHWARZ_RAS, SCHWARZ_AS, SCHWARZ_SAP = 0, 1, 2
 PRECOND_NONE, PRECOND_RAS = 0, 1
 OK, EINVAL, ENOMEM, EUNITARITY, ENOTCONV, EBREAKDOWN, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 PENDING = 1
@@ -34,28 +35,31 @@ class WclError(RuntimeError):
 
 class RasParams(C.Structure):
     _fields_ = [("block", C.c_int * 4), ("s", C.c_int), ("n_ras", C.c_int), ("n_dominv", C.c_int),
-                ("storage", C.c_int), ("kernel", C.c_int)]
+                ("storage", C.c_int), ("kernel", C.c_int), ("block_solver", C.c_int), ("schwarz", C.c_int)]
 
     @classmethod
-    def make(cls, block=(4, 4, 4, 4), s=0, n_ras=3, n_dominv=4, storage=F32, kernel=BLOCK_AUTO):
-        return cls((C.c_int * 4)(*block), s, n_ras, n_dominv, storage, kernel)
+    def make(cls, block=(4, 4, 4, 4), s=0, n_ras=3, n_dominv=4, storage=F32, kernel=BLOCK_AUTO,
+             block_solver=DOMSOLVE_MR, schwarz=SCHWARZ_RAS):
+        return cls((C.c_int * 4)(*block), s, n_ras, n_dominv, storage, kernel, block_solver, schwarz)
 
 
 class SolverParams(C.Structure):
     _fields_ = [("tol_outer", C.c_double), ("tol_inner", C.c_double), ("max_outer", C.c_int),
-                ("max_inner", C.c_int), ("max_restarts", C.c_int), ("precond", C.c_int), ("ras", RasParams)]
+                ("max_inner", C.c_int), ("max_restarts", C.c_int), ("precond", C.c_int), ("ras", RasParams),
+                ("even_odd", C.c_int), ("timers", C.c_int)]
 
     @classmethod
     def make(cls, tol_outer=1e-10, tol_inner=1e-4, max_outer=200, max_inner=100, max_restarts=10,
-             precond=PRECOND_RAS, ras=None):
+             precond=PRECOND_RAS, ras=None, even_odd=0, timers=0):
         return cls(tol_outer, tol_inner, max_outer, max_inner, max_restarts, precond,
-                   ras if ras is not None else RasParams.make())
+                   ras if ras is not None else RasParams.make(), even_odd, timers)
 
 
 class SolveStats(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("inner_iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
                 ("dslash_full", C.c_int64), ("dslash_block", C.c_int64), ("ras_sweeps", C.c_int64),
-                ("true_resid", C.c_double), ("ms_total", C.c_double)]
+                ("true_resid", C.c_double), ("ms_total", C.c_double), ("ms_dslash", C.c_double),
+                ("ms_dominv", C.c_double), ("ms_blas", C.c_double), ("ms_host", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -332,14 +336,16 @@ class Server:
 
 lib.wcl_autotune.restype = C.c_int
 lib.wcl_autotune.argtypes = [C.c_void_p, C.POINTER(SolverParams), C.c_double, C.c_double, C.c_void_p, C.c_int,
-                             C.c_char_p, C.POINTER(SolverParams), C.POINTER(C.c_double), C.c_void_p]
+                             C.c_int, C.c_char_p, C.POINTER(SolverParams), C.POINTER(C.c_double), C.c_void_p]
 
 
 def autotune(lat: Lattice, base: SolverParams, kappa: float, csw: float, eta: torch.Tensor, nrhs: int = 1,
-             cache_path: str | None = None, stream=None):
-    """Autotuned solver parameters for this lattice and source (see include/wcl.h)."""
+             cache_path: str | None = None, stream=None, storage=None):
+    """Autotuned solver parameters for this lattice, timed on the tuning source
+    eta (see include/wcl.h).  storage: None = FP32 and FP16, or F32 / F16 only."""
     best = SolverParams()
     ms = C.c_double()
-    check(lib.wcl_autotune(lat.h, C.byref(base), kappa, csw, _ptr(eta), nrhs,
+    mask = 0 if storage is None else (1 if storage == F32 else 2)
+    check(lib.wcl_autotune(lat.h, C.byref(base), kappa, csw, _ptr(eta), nrhs, mask,
                            cache_path.encode() if cache_path else None, C.byref(best), C.byref(ms), _stream(stream)))
     return best, ms.value

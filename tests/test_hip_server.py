@@ -121,3 +121,35 @@ def test_oversized_request_rejected(W, ctx):
         srv.register_gauge(2, CONFIGS[2], I.random_gauge(CONFIGS[2], 0.5, 1))
     assert e.value.code == W.ENOMEM
     srv.close()
+
+
+def test_mixed_sizes_under_a_tight_budget_drain(W, ctx):
+    """Requests of two lattice sizes under a budget that holds the resident
+    fields and a little more than one large solve: idle slots keep the small
+    lattice's workspaces, so a large request is admitted only after they are
+    released.  Every request must finish (no stalled queue) and converge."""
+    import time
+    g1, g2 = I.random_gauge(CONFIGS[1], 0.5, 1), I.random_gauge(CONFIGS[2], 0.5, 1)
+    resident = 0
+    for d in CONFIGS.values():
+        V = int(np.prod(d))
+        resident += V * 4 * 12 * (8 + 4 + 2) + V * (72 * 8 + 72 * 4 + 144) + 8192
+    V2 = int(np.prod(CONFIGS[2]))
+    need_large = V2 * (8 * 192 + 10 * 96 + 4 * 52 + 2 * 192 + 192) + 6 * 24 * V2 // 64 + (1 << 20)
+    srv = W.Server(ctx, max_slots=2, hbm_budget=resident + int(1.3 * need_large))
+    srv.register_gauge(1, CONFIGS[1], g1)
+    srv.register_gauge(2, CONFIGS[2], g2)
+    order = [1, 1, 2, 1, 2, 2, 1, 1, 2]
+    tickets = [srv.submit(c, 0.12, 1.0, I.gaussian_source(CONFIGS[c], 50 + k)) for k, c in enumerate(order)]
+    pending, results = set(tickets), {}
+    deadline = time.monotonic() + 90
+    while pending and time.monotonic() < deadline:
+        for t in list(pending):
+            r = srv.poll(t)
+            if r is not None:
+                results[t] = r[1]
+                pending.discard(t)
+        time.sleep(0.002)
+    assert not pending, f"{len(pending)} requests never finished"
+    assert all(r["status"] == 0 and r["converged"] == 1 for r in results.values())
+    srv.close()
