@@ -58,6 +58,13 @@ def _load():
         L.oracle_block_apply.argtypes = [vp, ip, C.c_int, C.c_int64, C.c_double, C.c_double, dp, dp]
         L.oracle_block_mr.argtypes = [vp, ip, C.c_int, C.c_int64, C.c_double, C.c_double, C.c_int, dp, dp]
         L.oracle_ras.argtypes = [vp, ip, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, dp, dp]
+        L.oracle_schwarz.argtypes = [vp, ip, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                                     C.c_double, dp, dp]
+        L.oracle_block_solve.argtypes = [vp, ip, C.c_int, C.c_int64, C.c_double, C.c_double, C.c_int, C.c_int,
+                                         dp, dp]
+        L.oracle_site_term_inverse.argtypes = [vp, C.c_double, C.c_double, C.c_int64, i64p, dp]
+        L.oracle_apply_schur.argtypes = [vp, C.c_double, C.c_double, dp, dp]
+        L.oracle_eo_solve.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int, dp, dp, ip, dp]
         L.oracle_bicgstab.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int, dp, dp, ip, dp]
         L.oracle_nested.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int,
                                     C.c_int, ip, C.c_int, C.c_int, C.c_int, dp, dp, ip, dp]
@@ -178,6 +185,53 @@ class Oracle:
         if rc != 0:
             raise ValueError(self.lib.oracle_last_error().decode())
         return phi
+
+    # domain solvers and Schwarz iterations: 0 = MR / RAS (Algorithm 1),
+    # 1 = block Jacobi / additive, 2 = truncated BiCGStab / multiplicative
+    def schwarz(self, eta, kappa, csw, block, s, n_ras, n_dominv, solver=0, schwarz=0, exact=False):
+        eta = _c128(eta, (self.V, 4, 3))
+        phi = np.zeros_like(eta)
+        b = np.array(block, dtype=np.int32)
+        rc = self.lib.oracle_schwarz(self.h, _ip(b), int(s), int(n_ras), int(n_dominv), int(bool(exact)),
+                                     int(solver), int(schwarz), kappa, csw, _dp(eta), _dp(phi))
+        if rc != 0:
+            raise ValueError(self.lib.oracle_last_error().decode())
+        return phi
+
+    def block_solve(self, block, s, blk, rhs_ext, kappa, csw, solver, n) -> np.ndarray:
+        _, ev = self.decomp(block, s)
+        rhs_ext = _c128(rhs_ext, (ev, 4, 3))
+        out = np.zeros_like(rhs_ext)
+        b = np.array(block, dtype=np.int32)
+        if self.lib.oracle_block_solve(self.h, _ip(b), int(s), int(blk), kappa, csw, int(solver), int(n),
+                                       _dp(rhs_ext), _dp(out)) != 0:
+            raise ValueError("bad block or solver")
+        return out
+
+    def site_term_inverse(self, kappa, csw, sites=None) -> np.ndarray:
+        sites = np.arange(self.V, dtype=np.int64) if sites is None else np.ascontiguousarray(sites, dtype=np.int64)
+        out = np.zeros((len(sites), 12, 12), dtype=np.complex128)
+        if self.lib.oracle_site_term_inverse(self.h, kappa, csw, len(sites), _i64p(sites), _dp(out)) != 0:
+            raise ValueError("singular site term")
+        return out
+
+    def apply_schur(self, psi, kappa, csw) -> np.ndarray:
+        psi = _c128(psi, (self.V, 4, 3))
+        out = np.zeros_like(psi)
+        if self.lib.oracle_apply_schur(self.h, kappa, csw, _dp(psi), _dp(out)) != 0:
+            raise ValueError(self.lib.oracle_last_error().decode())
+        return out
+
+    def eo_solve(self, eta, kappa, csw, tol=1e-10, max_iter=10000):
+        eta = _c128(eta, (self.V, 4, 3))
+        phi = np.zeros_like(eta)
+        info = np.zeros(3, np.int32)
+        rr = np.zeros(1)
+        rc = self.lib.oracle_eo_solve(self.h, kappa, csw, tol, int(max_iter), _dp(eta), _dp(phi), _ip(info), _dp(rr))
+        if rc < 0:
+            raise ValueError(self.lib.oracle_last_error().decode())
+        return phi, {"iters": int(info[0]), "restarts": int(info[1]), "converged": bool(info[2]),
+                     "rel_resid": float(rr[0])}
 
     def bicgstab(self, eta, kappa, csw, tol=1e-10, max_iter=10000):
         eta = _c128(eta, (self.V, 4, 3))

@@ -20,6 +20,15 @@
 //     restriction, sum, phi += v, r -= D v) ................ Sec. 2, Algorithm 1
 //   * fixed-iteration domain solver (read as minimal
 //     residual, N_dominv steps, zero start) ................ Sec. 2
+//     other readings: block Jacobi with the site term as
+//     the diagonal, and BiCGStab truncated to N_dominv
+//     iterations ........................................... Sec. 2
+//   * additive Schwarz (whole extended solutions summed,
+//     Richardson refinement) and multiplicative Schwarz
+//     (two colours of domains, residual updated between) ... Sec. 1-2
+//   * even-odd reduction to the Schur complement on the
+//     even sites (not in the paper; an accelerator of the
+//     same solve, using the 12x12 site-term inverse)
 //   * BiCGStab, right preconditioning D K chi = eta ......... Sec. 2, Eq. (3)
 //   * mixed-precision nested BiCGStab (outer solver whose
 //     preconditioner is an inner BiCGStab) ................. Sec. 3
@@ -28,7 +37,11 @@
 // parity pinned by: free-field plane-wave closed form, gamma5-hermiticity,
 // gauge covariance, uniform abelian field closed form for the clover term,
 // dense brute force on 2^4, the Eq. (2) identity for RAS, the exact-block RAS
-// invariant and BiCGStab against dense LU (see tests/test_oracle_*.py).
+// invariant, BiCGStab against dense LU, the extended-domain membership rule
+// of Sec. 4, the Neumann series of block Jacobi, BiCGStab's Galerkin and
+// minimal-residual conditions, the dense additive-Schwarz identity, the dense
+// error propagator of the multiplicative iteration and the dense Schur
+// complement (see tests/test_oracle_*.py).
 
 #include <algorithm>
 #include <cmath>
@@ -276,6 +289,78 @@ void apply_D(const Lattice& lat, double kappa, double csw, const cplx* psi, cplx
     for (int64_t x = 0; x < lat.V; ++x) D_at(lat, kappa, csw, whole, x, out + x * 12);
 }
 
+// The hopping part of D alone at x (every term of D_at but the site term):
+//   out = -kappa sum_mu [ (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu) ],
+// hops to sites the accessor reports as outside dropped.
+void hops_at(const Lattice& lat, double kappa, const Fetch& fetch, int64_t x, cplx* out /*[12]*/) {
+    for (int i = 0; i < 12; ++i) out[i] = 0.0;
+    cplx one_minus[4][4], one_plus[4][4];
+    for (int mu = 0; mu < 4; ++mu) {
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                cplx id = (a == b) ? 1.0 : 0.0;
+                one_minus[a][b] = id - DIRAC.g[mu][a][b];
+                one_plus[a][b] = id + DIRAC.g[mu][a][b];
+            }
+        double ph;
+        int64_t xf = lat.hop(x, mu, +1, &ph);
+        if (const cplx* pf = fetch(xf)) add_spin_colour(one_minus, lat.link(x, mu), pf, -kappa * ph, out);
+        int64_t xb = lat.hop(x, mu, -1, &ph);
+        if (const cplx* pb = fetch(xb)) add_spin_colour(one_plus, dag(lat.link(xb, mu)), pb, -kappa * ph, out);
+    }
+}
+
+// The site term A(x) = 1 + c_sw kappa C(x) as a 12x12 matrix.
+void site_term(const Lattice& lat, double kappa, double csw, int64_t x, cplx* A /*[144]*/) {
+    cplx tmp[144];
+    const cplx* C = clover_of(lat, x, tmp);
+    for (int i = 0; i < 12; ++i)
+        for (int j = 0; j < 12; ++j) A[i * 12 + j] = (i == j ? 1.0 : 0.0) + csw * kappa * C[i * 12 + j];
+}
+
+// Inverse of a general n x n complex matrix by Gauss-Jordan elimination with
+// partial pivoting; false if a pivot vanishes.
+bool invert(int n, const cplx* A, cplx* Ainv) {
+    std::vector<cplx> M(A, A + n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Ainv[i * n + j] = (i == j) ? 1.0 : 0.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::abs(M[r * n + c]) > std::abs(M[piv * n + c])) piv = r;
+        if (std::abs(M[piv * n + c]) == 0.0) return false;
+        if (piv != c)
+            for (int j = 0; j < n; ++j) {
+                std::swap(M[c * n + j], M[piv * n + j]);
+                std::swap(Ainv[c * n + j], Ainv[piv * n + j]);
+            }
+        const cplx inv = 1.0 / M[c * n + c];
+        for (int j = 0; j < n; ++j) {
+            M[c * n + j] *= inv;
+            Ainv[c * n + j] *= inv;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const cplx f = M[r * n + c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < n; ++j) {
+                M[r * n + j] -= f * M[c * n + j];
+                Ainv[r * n + j] -= f * Ainv[c * n + j];
+            }
+        }
+    }
+    return true;
+}
+
+// y = M x for a 12x12 matrix and a 12-component site vector.
+void matvec12(const cplx* M, const cplx* x, cplx* y) {
+    for (int i = 0; i < 12; ++i) {
+        cplx t = 0.0;
+        for (int j = 0; j < 12; ++j) t += M[i * 12 + j] * x[j];
+        y[i] = t;
+    }
+}
+
 // ------------------------------------------------------ BLAS-1 (FP64) ----
 cplx dot(const std::vector<cplx>& a, const std::vector<cplx>& b) {
     cplx s = 0.0;
@@ -481,15 +566,126 @@ void mr_solve(BlockOp& op, double kappa, double csw, const std::vector<cplx>& b,
     }
 }
 
+// Block Jacobi, zero start, exactly n steps: x <- x + A^{-1} (b - D x), A the
+// site term of each site of the domain (the diagonal blocks of D_{Omega'}).
+void jacobi_solve(BlockOp& op, double kappa, double csw, const std::vector<cplx>& b, std::vector<cplx>& x, int n) {
+    const size_t m = b.size();
+    std::vector<cplx> Ainv(op.sites.size() * 144), Dx(m), r(m);
+    for (size_t k = 0; k < op.sites.size(); ++k) {
+        cplx A[144];
+        site_term(op.lat, kappa, csw, op.sites[k], A);
+        invert(12, A, &Ainv[k * 144]);
+    }
+    x.assign(m, 0.0);
+    for (int it = 0; it < n; ++it) {
+        op.apply(kappa, csw, x, Dx);
+        for (size_t i = 0; i < m; ++i) r[i] = b[i] - Dx[i];
+        for (size_t k = 0; k < op.sites.size(); ++k) {
+            cplx z[12];
+            matvec12(&Ainv[k * 144], &r[k * 12], z);
+            for (int i = 0; i < 12; ++i) x[k * 12 + i] += z[i];
+        }
+    }
+}
+
+// BiCGStab truncated to exactly n iterations from zero, no restarts and no
+// early exit.  A vanishing denominator makes its coefficient zero:
+// alpha = 0 when <rhat, v> = 0, omega = 0 when |t| = 0, beta = 0 when
+// rho_old = 0 or omega = 0 (so a zero right-hand side gives x = 0).
+void bicgstab_fixed(BlockOp& op, double kappa, double csw, const std::vector<cplx>& b, std::vector<cplx>& x, int n) {
+    const size_t m = b.size();
+    std::vector<cplx> r = b, rhat = b, p(m, 0.0), v(m, 0.0), s(m), t(m);
+    x.assign(m, 0.0);
+    cplx rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    for (int it = 0; it < n; ++it) {
+        const cplx rho = dot(rhat, r);
+        const cplx beta = (rho_old != 0.0 && omega != 0.0) ? (rho / rho_old) * (alpha / omega) : cplx(0.0);
+        for (size_t i = 0; i < m; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        op.apply(kappa, csw, p, v);
+        const cplx rv = dot(rhat, v);
+        alpha = (rv != 0.0) ? rho / rv : cplx(0.0);
+        for (size_t i = 0; i < m; ++i) s[i] = r[i] - alpha * v[i];
+        op.apply(kappa, csw, s, t);
+        const double tt = norm2(t);
+        omega = (tt > 0.0) ? dot(t, s) / tt : cplx(0.0);
+        for (size_t i = 0; i < m; ++i) {
+            x[i] += alpha * p[i] + omega * s[i];
+            r[i] = s[i] - omega * t[i];
+        }
+        rho_old = rho;
+    }
+}
+
+enum { DOM_MR = 0, DOM_JACOBI = 1, DOM_BICGSTAB = 2 };
+enum { SCH_RAS = 0, SCH_AS = 1, SCH_SAP = 2 };
+
 struct RasParams {
     int b[4];
     int s;
     int n_ras;
     int n_dominv;
-    int exact;   // 1: domain solve by BiCGStab to 1e-14 instead of MR
+    int exact;     // 1: domain solve by BiCGStab to 1e-14 instead of the fixed-iteration solver
+    int solver;    // DOM_*: the fixed-iteration domain solver (Sec. 2)
+    int schwarz;   // SCH_*: restricted additive (Algorithm 1), additive, multiplicative
 };
 
-// Algorithm 1: phi = K_RAS eta.
+// Colour of domain blk for the multiplicative iteration: parity of the sum of
+// its block coordinates.
+int block_colour(const Decomp& d, int64_t blk) {
+    int c = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        c += (int)(blk % d.nb[mu]);
+        blk /= d.nb[mu];
+    }
+    return c & 1;
+}
+
+// Solves every domain of the given colour (-1: all) on the residual r and
+// sums the results into v: the restriction R_{Omega_i} (owned sites only) for
+// the restricted iterations, the whole extended solution (overlaps add up)
+// for the additive one.
+void domain_pass(const Lattice& lat, const Decomp& d, const RasParams& P, double kappa, double csw,
+                 const std::vector<cplx>& r, int colour, std::vector<cplx>& v) {
+    std::fill(v.begin(), v.end(), cplx(0.0));
+    std::vector<std::vector<cplx>> sol(d.nblocks);
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t blk = 0; blk < d.nblocks; ++blk) {
+        if (colour >= 0 && block_colour(d, blk) != colour) continue;
+        BlockOp op(lat, d, blk);
+        const std::vector<int64_t>& sites = op.sites;
+        // projection r_{Omega'} = P r
+        std::vector<cplx> rb(sites.size() * 12);
+        for (size_t k = 0; k < sites.size(); ++k)
+            for (int i = 0; i < 12; ++i) rb[k * 12 + i] = r[sites[k] * 12 + i];
+        // domain solve with the Dirichlet boundary condition
+        if (P.exact) {
+            VecOp A = [&](const std::vector<cplx>& a, std::vector<cplx>& o) {
+                o.resize(a.size());
+                op.apply(kappa, csw, a, o);
+            };
+            bicgstab(A, nullptr, rb, sol[blk], 1e-14, 100000);
+        } else if (P.solver == DOM_JACOBI) {
+            jacobi_solve(op, kappa, csw, rb, sol[blk], P.n_dominv);
+        } else if (P.solver == DOM_BICGSTAB) {
+            bicgstab_fixed(op, kappa, csw, rb, sol[blk], P.n_dominv);
+        } else {
+            mr_solve(op, kappa, csw, rb, sol[blk], P.n_dominv);
+        }
+    }
+    // the sum over domains, in domain order
+    for (int64_t blk = 0; blk < d.nblocks; ++blk) {
+        if (sol[blk].empty()) continue;
+        std::vector<int64_t> sites = ext_sites(lat, d, blk);
+        for (size_t k = 0; k < sites.size(); ++k)
+            if (P.schwarz == SCH_AS || owned(lat, d, blk, sites[k]))
+                for (int i = 0; i < 12; ++i) v[sites[k] * 12 + i] += sol[blk][k * 12 + i];
+    }
+}
+
+// Algorithm 1: phi = K_RAS eta, and the other Schwarz iterations of Sec. 1-2:
+// the additive one (the whole extended solutions summed, refined by the same
+// Richardson update) and the multiplicative one (each sweep solves the
+// colour-0 domains, updates phi and r, then the colour-1 domains).
 bool ras(const Lattice& lat, const RasParams& P, double kappa, double csw,
          const std::vector<cplx>& eta, std::vector<cplx>& phi) {
     Decomp d;
@@ -497,36 +693,75 @@ bool ras(const Lattice& lat, const RasParams& P, double kappa, double csw,
     const int64_t n = lat.V * 12;
     std::vector<cplx> r = eta, v(n), Dv(n);
     phi.assign(n, 0.0);
-    for (int j = 0; j < P.n_ras; ++j) {
-        std::fill(v.begin(), v.end(), cplx(0.0));
-#pragma omp parallel for schedule(dynamic)
-        for (int64_t blk = 0; blk < d.nblocks; ++blk) {
-            BlockOp op(lat, d, blk);
-            const std::vector<int64_t>& sites = op.sites;
-            // projection r_{Omega'} = P r
-            std::vector<cplx> rb(sites.size() * 12), vb;
-            for (size_t k = 0; k < sites.size(); ++k)
-                for (int i = 0; i < 12; ++i) rb[k * 12 + i] = r[sites[k] * 12 + i];
-            // domain solve with the Dirichlet boundary condition
-            if (P.exact) {
-                VecOp A = [&](const std::vector<cplx>& a, std::vector<cplx>& o) {
-                    o.resize(a.size());
-                    op.apply(kappa, csw, a, o);
-                };
-                bicgstab(A, nullptr, rb, vb, 1e-14, 100000);
-            } else {
-                mr_solve(op, kappa, csw, rb, vb, P.n_dominv);
-            }
-            // restriction to Omega_i; the Omega_i partition the lattice
-            for (size_t k = 0; k < sites.size(); ++k)
-                if (owned(lat, d, blk, sites[k]))
-                    for (int i = 0; i < 12; ++i) v[sites[k] * 12 + i] = vb[k * 12 + i];
+    const int passes = P.schwarz == SCH_SAP ? 2 : 1;
+    for (int j = 0; j < P.n_ras; ++j)
+        for (int c = 0; c < passes; ++c) {
+            domain_pass(lat, d, P, kappa, csw, r, P.schwarz == SCH_SAP ? c : -1, v);
+            for (int64_t i = 0; i < n; ++i) phi[i] += v[i];
+            apply_D(lat, kappa, csw, v.data(), Dv.data());
+            for (int64_t i = 0; i < n; ++i) r[i] -= Dv[i];
         }
-        for (int64_t i = 0; i < n; ++i) phi[i] += v[i];
-        apply_D(lat, kappa, csw, v.data(), Dv.data());
-        for (int64_t i = 0; i < n; ++i) r[i] -= Dv[i];
-    }
     return true;
+}
+
+// ------------------------------------------------------ even-odd --------
+// Site parity (x + y + z + t) mod 2.  With every extent even, every hop joins
+// sites of opposite parity, so D = [[A_ee, D_eo], [D_oe, A_oo]] and D phi = eta
+// reduces to the Schur complement on the even sites:
+//   Dhat = A_ee - D_eo A_oo^{-1} D_oe,
+//   Dhat phi_e = eta_e - D_eo A_oo^{-1} eta_o,
+//   phi_o = A_oo^{-1} (eta_o - D_oe phi_e).
+int parity(const Lattice& lat, int64_t x) {
+    int c[4];
+    lat.coords(x, c);
+    return (c[0] + c[1] + c[2] + c[3]) & 1;
+}
+
+bool even_extents(const Lattice& lat) {
+    for (int mu = 0; mu < 4; ++mu)
+        if (lat.L[mu] % 2) return false;
+    return true;
+}
+
+// out_p = A_pp^{-1} in_p at the sites of parity p (other sites left alone).
+void site_inverse_apply(const Lattice& lat, double kappa, double csw, int p, const cplx* in, cplx* out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < lat.V; ++x) {
+        if (parity(lat, x) != p) continue;
+        cplx A[144], Ai[144];
+        site_term(lat, kappa, csw, x, A);
+        invert(12, A, Ai);
+        matvec12(Ai, in + x * 12, out + x * 12);
+    }
+}
+
+// out_p = (hopping part of D) in, at the sites of parity p, reading only the
+// opposite parity of in; other sites of out left alone.
+void hops_parity(const Lattice& lat, double kappa, int p, const cplx* in, cplx* out) {
+    Fetch other = [&lat, in, p](int64_t y) -> const cplx* { return parity(lat, y) != p ? in + y * 12 : nullptr; };
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < lat.V; ++x)
+        if (parity(lat, x) == p) hops_at(lat, kappa, other, x, out + x * 12);
+}
+
+// out = Dhat psi on the even sites, 0 on the odd sites (psi's odd sites unused).
+void apply_schur(const Lattice& lat, double kappa, double csw, const cplx* psi, cplx* out) {
+    const int64_t n = lat.V * 12;
+    std::vector<cplx> h(n, 0.0), t(n, 0.0), w(n, 0.0);
+    hops_parity(lat, kappa, 1, psi, h.data());                 // D_oe psi_e
+    site_inverse_apply(lat, kappa, csw, 1, h.data(), t.data());  // A_oo^{-1} D_oe psi_e
+    hops_parity(lat, kappa, 0, t.data(), w.data());            // D_eo A_oo^{-1} D_oe psi_e
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < lat.V; ++x) {
+        if (parity(lat, x) != 0) {
+            for (int i = 0; i < 12; ++i) out[x * 12 + i] = 0.0;
+            continue;
+        }
+        cplx A[144], a[12];
+        site_term(lat, kappa, csw, x, A);
+        matvec12(A, psi + x * 12, a);
+        for (int i = 0; i < 12; ++i) out[x * 12 + i] = a[i] - w[x * 12 + i];
+    }
 }
 
 thread_local char g_err[256] = "";
@@ -665,15 +900,20 @@ int oracle_block_mr(oracle_lattice* h, const int* b, int s, int64_t blk, double 
     return 0;
 }
 
-// phi = K_RAS eta (Algorithm 1). exact = 1 solves each domain to 1e-14.
-int oracle_ras(oracle_lattice* h, const int* b, int s, int n_ras, int n_dominv, int exact, double kappa,
-               double csw, const double* eta, double* phi) {
+// phi = K eta for the Schwarz iteration `schwarz` (0 = RAS, Algorithm 1;
+// 1 = additive; 2 = multiplicative) with domain solver `solver` (0 = MR,
+// 1 = block Jacobi, 2 = truncated BiCGStab). exact = 1 solves each domain to
+// 1e-14 instead.
+int oracle_schwarz(oracle_lattice* h, const int* b, int s, int n_ras, int n_dominv, int exact, int solver,
+                   int schwarz, double kappa, double csw, const double* eta, double* phi) {
     RasParams P;
     for (int mu = 0; mu < 4; ++mu) P.b[mu] = b[mu];
     P.s = s;
     P.n_ras = n_ras;
     P.n_dominv = n_dominv;
     P.exact = exact;
+    P.solver = solver;
+    P.schwarz = schwarz;
     const int64_t n = h->lat.V * 12;
     const cplx* pe = reinterpret_cast<const cplx*>(eta);
     std::vector<cplx> e(pe, pe + n), f;
@@ -683,6 +923,109 @@ int oracle_ras(oracle_lattice* h, const int* b, int s, int n_ras, int n_dominv, 
     }
     std::memcpy(phi, f.data(), n * sizeof(cplx));
     return 0;
+}
+
+// x = n iterations of domain solver `solver` (as oracle_schwarz) on block blk
+// from zero, right-hand side rhs (ext_volume sites, oracle_block_sites order).
+int oracle_block_solve(oracle_lattice* h, const int* b, int s, int64_t blk, double kappa, double csw, int solver,
+                       int n, const double* rhs, double* x) {
+    Decomp d;
+    if (!make_decomp(h->lat, b, s, &d) || blk < 0 || blk >= d.nblocks || solver < 0 || solver > 2) return -1;
+    BlockOp op(h->lat, d, blk);
+    const cplx* pr = reinterpret_cast<const cplx*>(rhs);
+    std::vector<cplx> vb(pr, pr + op.sites.size() * 12), vx;
+    if (solver == DOM_JACOBI) jacobi_solve(op, kappa, csw, vb, vx, n);
+    else if (solver == DOM_BICGSTAB) bicgstab_fixed(op, kappa, csw, vb, vx, n);
+    else mr_solve(op, kappa, csw, vb, vx, n);
+    std::memcpy(x, vx.data(), vx.size() * sizeof(cplx));
+    return 0;
+}
+
+// A(x)^{-1} = (1 + c_sw kappa C(x))^{-1} as [n][12][12] complex at the listed
+// sites; -1 if some A(x) is singular.
+int oracle_site_term_inverse(oracle_lattice* h, double kappa, double csw, int64_t n, const int64_t* sites,
+                             double* out) {
+    cplx* o = reinterpret_cast<cplx*>(out);
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+    for (int64_t k = 0; k < n; ++k) {
+        cplx A[144];
+        site_term(h->lat, kappa, csw, sites[k], A);
+        if (!invert(12, A, o + k * 144)) ++bad;
+    }
+    return bad ? -1 : 0;
+}
+
+// phi = K_RAS eta (Algorithm 1). exact = 1 solves each domain to 1e-14.
+int oracle_ras(oracle_lattice* h, const int* b, int s, int n_ras, int n_dominv, int exact, double kappa,
+               double csw, const double* eta, double* phi) {
+    RasParams P;
+    for (int mu = 0; mu < 4; ++mu) P.b[mu] = b[mu];
+    P.s = s;
+    P.n_ras = n_ras;
+    P.n_dominv = n_dominv;
+    P.exact = exact;
+    P.solver = DOM_MR;
+    P.schwarz = SCH_RAS;
+    const int64_t n = h->lat.V * 12;
+    const cplx* pe = reinterpret_cast<const cplx*>(eta);
+    std::vector<cplx> e(pe, pe + n), f;
+    if (!ras(h->lat, P, kappa, csw, e, f)) {
+        std::snprintf(g_err, sizeof g_err, "block shape does not tile the lattice");
+        return -1;
+    }
+    std::memcpy(phi, f.data(), n * sizeof(cplx));
+    return 0;
+}
+
+// out = Dhat psi (the even-odd Schur complement on the even sites, 0 on the
+// odd sites); -1 if an extent is odd.
+int oracle_apply_schur(oracle_lattice* h, double kappa, double csw, const double* psi, double* out) {
+    if (!even_extents(h->lat)) {
+        std::snprintf(g_err, sizeof g_err, "even-odd reduction needs even extents");
+        return -1;
+    }
+    apply_schur(h->lat, kappa, csw, reinterpret_cast<const cplx*>(psi), reinterpret_cast<cplx*>(out));
+    return 0;
+}
+
+// D phi = eta through the even-odd reduction: BiCGStab (tolerance tol on
+// the reduced system's recursive residual) on Dhat phi_e = eta_e - D_eo
+// A_oo^{-1} eta_o, then phi_o = A_oo^{-1}(eta_o - D_oe phi_e).
+// info = {iterations, restarts, converged}.
+int oracle_eo_solve(oracle_lattice* h, double kappa, double csw, double tol, int max_iter, const double* eta,
+                    double* phi, int* info, double* rel_resid) {
+    const Lattice& lat = h->lat;
+    if (!even_extents(lat)) {
+        std::snprintf(g_err, sizeof g_err, "even-odd reduction needs even extents");
+        return -1;
+    }
+    const int64_t n = lat.V * 12;
+    const cplx* pe = reinterpret_cast<const cplx*>(eta);
+    std::vector<cplx> t(n, 0.0), w(n, 0.0), be(n, 0.0), x;
+    site_inverse_apply(lat, kappa, csw, 1, pe, t.data());   // A_oo^{-1} eta_o
+    hops_parity(lat, kappa, 0, t.data(), w.data());         // D_eo A_oo^{-1} eta_o
+    for (int64_t y = 0; y < lat.V; ++y)
+        if (parity(lat, y) == 0)
+            for (int i = 0; i < 12; ++i) be[y * 12 + i] = pe[y * 12 + i] - w[y * 12 + i];
+    VecOp A = [&](const std::vector<cplx>& a, std::vector<cplx>& o) {
+        o.resize(a.size());
+        apply_schur(lat, kappa, csw, a.data(), o.data());
+    };
+    SolveInfo si = bicgstab(A, nullptr, be, x, tol, max_iter);
+    // odd sites: phi_o = A_oo^{-1}(eta_o - D_oe phi_e)
+    std::vector<cplx> hx(n, 0.0), ro(n, 0.0);
+    hops_parity(lat, kappa, 1, x.data(), hx.data());
+    for (int64_t y = 0; y < lat.V; ++y)
+        if (parity(lat, y) == 1)
+            for (int i = 0; i < 12; ++i) ro[y * 12 + i] = pe[y * 12 + i] - hx[y * 12 + i];
+    site_inverse_apply(lat, kappa, csw, 1, ro.data(), x.data());
+    std::memcpy(phi, x.data(), n * sizeof(cplx));
+    info[0] = si.iters;
+    info[1] = si.restarts;
+    info[2] = si.converged;
+    *rel_resid = si.rel_resid;
+    return si.converged ? 0 : 1;
 }
 
 // Plain BiCGStab on D phi = eta; info = {iterations, restarts, converged}
@@ -720,6 +1063,8 @@ int oracle_nested(oracle_lattice* h, double kappa, double csw, double tol, int m
     P.n_ras = n_ras;
     P.n_dominv = n_dominv;
     P.exact = 0;
+    P.solver = DOM_MR;
+    P.schwarz = SCH_RAS;
     Decomp d;
     if (use_ras && !make_decomp(h->lat, P.b, P.s, &d)) {
         std::snprintf(g_err, sizeof g_err, "block shape does not tile the lattice");
