@@ -96,7 +96,10 @@ typedef struct wcl_server wcl_server;
  * for the gauge/clover fields and the sweep-internal residual/correction
  * fields.  block_solver and schwarz select the variants above (0 = the
  * defaults: MR domain solves inside RAS); the Jacobi and BiCGStab domain
- * solvers and the AS and SAP iterations run on the split path. */
+ * solvers and the AS and SAP iterations run on the split path.  AS needs
+ * s <= block[mu] in every split direction (WCL_EINVAL otherwise); its
+ * Richardson refinement (n_ras > 1) diverges when overlaps are counted twice,
+ * so as a preconditioner it is normally used with n_ras = 1. */
 typedef struct wcl_ras_params {
     int block[4];
     int s;
@@ -217,8 +220,13 @@ int wcl_apply_D_blocks(wcl_lattice* lat, const wcl_ras_params* ras, double kappa
 /* Number of domains and extended-domain volume for ras->block, ras->s. */
 int wcl_block_info(const wcl_lattice* lat, const wcl_ras_params* ras, int64_t* nblocks, int64_t* ext_volume);
 
-/* v = K_RAS r (Algorithm 1 / Eq. (2)) for nrhs FP32 fields; r and v are
- * FP32 device buffers that must not alias. */
+/* v = K r for nrhs FP32 fields: n_ras sweeps of the Schwarz iteration
+ * ras->schwarz (RAS: Algorithm 1 / Eq. (2); AS and SAP: Sec. 1-2, see
+ * WCL_SCHWARZ_*) with n_dominv iterations of the domain solver
+ * ras->block_solver on every domain.  r and v are FP32 device buffers that
+ * must not alias.  The block Jacobi solver builds the site-term inverse
+ * (1 + c_SW kappa C)^{-1} once per (kappa, c_SW) and returns WCL_EINVAL if
+ * it is singular at some site.  May allocate workspace on first use. */
 int wcl_ras_precondition(wcl_lattice* lat, const wcl_ras_params* ras, double kappa, double csw, const void* r_dev,
                          void* v_dev, int nrhs, void* stream);
 

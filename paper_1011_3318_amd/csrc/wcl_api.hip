@@ -5,6 +5,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstring>
+#include <atomic>
 #include <vector>
 
 #include "wcl_kernels.h"
@@ -134,9 +135,11 @@ int wcl_create_lattice(wcl_ctx* ctx, const int dims[4], const int bc[4], wcl_lat
         wcl_set_error("wcl_create_lattice: volume %lld too large", (long long)V);
         return WCL_EINVAL;
     }
+    static std::atomic<uint64_t> next_uid{1};
     auto* lat = new wcl_lattice;
     lat->ctx = ctx;
     lat->V = V;
+    lat->uid = next_uid++;
     Geom& g = lat->g;
     const int caps[3] = {32, 32, 8};
     for (int mu = 0; mu < 4; ++mu) {
@@ -252,6 +255,7 @@ int wcl_compute_clover(wcl_lattice* lat) {
     WCL_CHECK(launch_clover_build(lat->g, lat->gauge[0], lat->clover[0], lat->clover[1], lat->clover[2], 0));
     WCL_HIP(hipDeviceSynchronize());
     lat->has_clover = true;
+    ++lat->clover_gen;
     return WCL_OK;
 }
 
@@ -276,7 +280,10 @@ int wcl_upload_clover(wcl_lattice* lat, const double* C) {
     if (rc == WCL_OK && hipDeviceSynchronize() != hipSuccess) rc = WCL_EHIP;
     wcl_dev_free(lat->ctx, stage, bytes);
     if (rc == WCL_EHIP) wcl_set_error("wcl_upload_clover: device copy or pack failed");
-    if (rc == WCL_OK) lat->has_clover = true;
+    if (rc == WCL_OK) {
+        lat->has_clover = true;
+        ++lat->clover_gen;
+    }
     return rc;
 }
 

@@ -36,29 +36,6 @@ WCL_DEV bool block_owned(const Blocks& B, const int lc[4]) {
     return o;
 }
 
-// projection: rho = P r on every extended site, x = 0
-template <int SRC>
-__global__ __launch_bounds__(256) void k_blk_project(BlockArgs a) {
-    const int per_rhs = a.B.nblocks * a.wpb;
-    const int rhs = blockIdx.x / per_rhs;
-    const int blk = (blockIdx.x % per_rhs) / a.wpb;
-    if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
-    const int l = (blockIdx.x % a.wpb) * 256 + threadIdx.x;
-    if (l >= a.B.ev) return;
-    int lc[4], x[4];
-    block_site(a.g, a.B, blk, l, lc, x);
-    float s[24];
-    SpinorIO<SRC>::load((const char*)a.src + rhs * a.src_stride, a.g.V, geom_index(a.g, x), s);
-    const int e = blk * a.B.ev + l;
-    f4v* rho = (f4v*)a.rho + rhs * a.ws_stride;
-    f4v* xs = (f4v*)a.x + rhs * a.ws_stride;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        rho[(size_t)q * a.NE + e] = f4v{s[4 * q], s[4 * q + 1], s[4 * q + 2], s[4 * q + 3]};
-        xs[(size_t)q * a.NE + e] = f4v{0.f, 0.f, 0.f, 0.f};
-    }
-}
-
 WCL_DEV void ws_load(const f4v* base, int NE, int e, float s[24]) {
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
@@ -72,6 +49,95 @@ WCL_DEV void ws_load(const f4v* base, int NE, int e, float s[24]) {
 WCL_DEV void ws_store(f4v* base, int NE, int e, const float s[24]) {
 #pragma unroll
     for (int q = 0; q < 6; ++q) base[(size_t)q * NE + e] = f4v{s[4 * q], s[4 * q + 1], s[4 * q + 2], s[4 * q + 3]};
+}
+
+// Colour of a domain for the multiplicative iteration: parity of the sum of
+// its block coordinates.
+WCL_DEV int block_colour(const Blocks& B, int blk) {
+    int c = 0;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        c += blk % B.nb[mu];
+        blk /= B.nb[mu];
+    }
+    return c & 1;
+}
+
+WCL_DEV bool skip_colour(const BlockArgs& a, int blk) { return a.colour >= 0 && block_colour(a.B, blk) != a.colour; }
+
+// End of a domain solve at extended site l with solution xv:
+//   whole: keep xv in the workspace x (the additive gather sums it);
+//   else restriction to the owned sites: out (FP32) = xv, or out += xv when
+//   accumulating over sweeps, and vj (storage precision) = xv when requested.
+// zero = the domain was not solved in this pass (other colour): its owned
+// sites get v = 0 (vj, and out unless accumulating).
+template <int VP>
+WCL_DEV void blk_finish(const BlockArgs& a, int rhs, int blk, int l, const float xv[24], bool zero) {
+    if (a.whole) {
+        ws_store((f4v*)a.x + rhs * a.ws_stride, a.NE, blk * a.B.ev + l, xv);
+        return;
+    }
+    int lc[4], x[4];
+    block_site(a.g, a.B, blk, l, lc, x);
+    if (!block_owned(a.B, lc)) return;
+    const int gi = geom_index(a.g, x);
+    char* out = (char*)a.out + rhs * a.out_stride;
+    float z[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) z[k] = zero ? 0.f : xv[k];
+    if (a.accumulate) {
+        if (!zero) {
+            float o[24];
+            SpinorIO<WCL_F32>::load(out, a.g.V, gi, o);
+#pragma unroll
+            for (int k = 0; k < 24; ++k) o[k] += z[k];
+            SpinorIO<WCL_F32>::store(out, a.g.V, gi, o);
+        }
+    } else {
+        SpinorIO<WCL_F32>::store(out, a.g.V, gi, z);
+    }
+    if (a.vj) SpinorIO<VP>::store((char*)a.vj + rhs * a.vj_stride, a.g.V, gi, z);
+}
+
+// Sum of the wpb partial triples of domain blk (fixed order).
+WCL_DEV void domain_sum3(const double* part, const BlockArgs& a, int rhs, int blk, double s[3]) {
+    const double* p = part + 3 * ((size_t)rhs * a.B.nblocks + blk) * a.wpb;
+    s[0] = s[1] = s[2] = 0.0;
+    for (int k = 0; k < a.wpb; ++k) {
+        s[0] += p[3 * k];
+        s[1] += p[3 * k + 1];
+        s[2] += p[3 * k + 2];
+    }
+}
+
+// projection: rho = P r on every extended site, x = 0.  BCG (truncated
+// BiCGStab): also rhat = rho and the partial sums of <rhat, rho>.
+template <int SRC, bool BCG>
+__global__ __launch_bounds__(256) void k_blk_project(BlockArgs a) {
+    const int per_rhs = a.B.nblocks * a.wpb;
+    const int rhs = blockIdx.x / per_rhs;
+    const int blk = (blockIdx.x % per_rhs) / a.wpb;
+    if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
+    if (skip_colour(a, blk)) return;
+    const int wl = blockIdx.x % a.wpb;
+    const int l = wl * 256 + threadIdx.x;
+    double d[3] = {0.0, 0.0, 0.0};
+    if (l < a.B.ev) {
+        int lc[4], x[4];
+        block_site(a.g, a.B, blk, l, lc, x);
+        float s[24], z[24];
+        SpinorIO<SRC>::load((const char*)a.src + rhs * a.src_stride, a.g.V, geom_index(a.g, x), s);
+        const int e = blk * a.B.ev + l;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) z[k] = 0.f;
+        ws_store((f4v*)a.rho + rhs * a.ws_stride, a.NE, e, s);
+        ws_store((f4v*)a.x + rhs * a.ws_stride, a.NE, e, z);
+        if constexpr (BCG) {
+            ws_store((f4v*)a.brh + rhs * a.ws_stride, a.NE, e, s);
+            site_dot3(s, s, d);
+        }
+    }
+    if constexpr (BCG) block_reduce3(d, a.bpart[0] + 3 * (((size_t)rhs * a.B.nblocks + blk) * a.wpb + wl));
 }
 
 // Workspace index of the neighbour of extended site lc in direction mu
@@ -105,13 +171,15 @@ WCL_DEV void blk_fetch(const BlockArgs& a, const f4v* rho, int base, int n, int 
     }
 }
 
-// q = D_{Omega'} rho on all extended sites; partials <q, rho>, <q, q> per workgroup
+// q = D_{Omega'} rho on all extended sites; partials per workgroup of
+// <q, rho> and <q, q>, or of <dhat, q> and <q, q> when dhat is set
 template <int GP>
 __global__ __launch_bounds__(256) void k_blk_dslash(BlockArgs a) {
     const int per_rhs = a.B.nblocks * a.wpb;
     const int rhs = blockIdx.x / per_rhs;
     const int blk = (blockIdx.x % per_rhs) / a.wpb;
     if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
+    if (skip_colour(a, blk)) return;
     const int wl = blockIdx.x % a.wpb;
     const int l = wl * 256 + threadIdx.x;
     double d[3] = {0, 0, 0};
@@ -144,7 +212,7 @@ __global__ __launch_bounds__(256) void k_blk_dslash(BlockArgs a) {
         float s0[24], u0[18], s1[24], u1[18];
         blk_fetch<GP>(a, rho, base, ni[0], 0, li[0], s0, u0);
 #define WCL_BHOP(K, SC, UC, SN, UN)                                                            \
-    if ((K) < 7) blk_fetch<GP>(a, rho, base, ni[(K) + 1], ((K) + 1) / 2, li[(K) + 1], SN, UN); \
+    if ((K) < 7) blk_fetch<GP>(a, rho, base, ni[((K) + 1) & 7], ((K) + 1) / 2, li[((K) + 1) & 7], SN, UN); \
     if (ni[K] >= 0) hop_compute<(K) / 2, ((K) % 2) == 0>(SC, UC, mk * ph[K], acc);
         WCL_BHOP(0, s0, u0, s1, u1)
         WCL_BHOP(1, s1, u1, s0, u0)
@@ -169,21 +237,45 @@ __global__ __launch_bounds__(256) void k_blk_dslash(BlockArgs a) {
             }
         }
         ws_store((f4v*)a.q + rhs * a.ws_stride, a.NE, e, acc);
+        if (a.dhat) {
+            float h[24];
+            ws_load((const f4v*)a.dhat + rhs * a.ws_stride, a.NE, e, h);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            float qr = acc[2 * k], qi = acc[2 * k + 1], rr = r0[2 * k], ri = r0[2 * k + 1];
-            d[0] += (double)(qr * rr + qi * ri);   // <q, rho>
-            d[1] += (double)(qr * ri - qi * rr);
-            d[2] += (double)(qr * qr + qi * qi);   // <q, q>
+            for (int k = 0; k < 12; ++k) {
+                float hr = h[2 * k], hi = h[2 * k + 1], qr = acc[2 * k], qi = acc[2 * k + 1];
+                d[0] += (double)(hr * qr + hi * qi);   // <dhat, q>
+                d[1] += (double)(hr * qi - hi * qr);
+                d[2] += (double)(qr * qr + qi * qi);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                float qr = acc[2 * k], qi = acc[2 * k + 1], rr = r0[2 * k], ri = r0[2 * k + 1];
+                d[0] += (double)(qr * rr + qi * ri);   // <q, rho>
+                d[1] += (double)(qr * ri - qi * rr);
+                d[2] += (double)(qr * qr + qi * qi);   // <q, q>
+            }
         }
     }
     block_reduce3(d, a.partial + 3 * (((size_t)rhs * a.B.nblocks + blk) * a.wpb + wl));
 }
 
+// Last-step write-out of a workgroup whose domain is not solved in this
+// pass (other colour): zeros at its owned sites.
+template <int VP>
+WCL_DEV bool colour_skip_finish(const BlockArgs& a, int rhs, int blk, int l, int last) {
+    if (!skip_colour(a, blk)) return false;
+    if (last && l < a.B.ev) {
+        float z[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) z[k] = 0.f;
+        blk_finish<VP>(a, rhs, blk, l, z, true);
+    }
+    return true;
+}
+
 // alpha = <q,rho>/<q,q> for the domain; x += alpha rho; rho -= alpha q.
-// On the last step the owned sites are written out (restriction):
-//   out (FP32) = x, or out += x when accumulating over sweeps,
-//   vj (storage precision) = x when requested.
+// On the last step the solution goes to blk_finish.
 template <int VP>
 __global__ __launch_bounds__(256) void k_blk_update(BlockArgs a, int last) {
     const int per_rhs = a.B.nblocks * a.wpb;
@@ -191,17 +283,13 @@ __global__ __launch_bounds__(256) void k_blk_update(BlockArgs a, int last) {
     const int blk = (blockIdx.x % per_rhs) / a.wpb;
     if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
     const int l = (blockIdx.x % a.wpb) * 256 + threadIdx.x;
+    if (colour_skip_finish<VP>(a, rhs, blk, l, last)) return;
     __shared__ float al[2];
     if (threadIdx.x == 0) {
-        const double* p = a.partial + 3 * ((size_t)rhs * a.B.nblocks + blk) * a.wpb;
-        double s0 = 0, s1 = 0, s2 = 0;
-        for (int k = 0; k < a.wpb; ++k) {
-            s0 += p[3 * k];
-            s1 += p[3 * k + 1];
-            s2 += p[3 * k + 2];
-        }
-        al[0] = s2 > 0 ? (float)(s0 / s2) : 0.f;
-        al[1] = s2 > 0 ? (float)(s1 / s2) : 0.f;
+        double s[3];
+        domain_sum3(a.partial, a, rhs, blk, s);
+        al[0] = s[2] > 0 ? (float)(s[0] / s[2]) : 0.f;
+        al[1] = s[2] > 0 ? (float)(s[1] / s[2]) : 0.f;
     }
     __syncthreads();
     if (l >= a.B.ev) return;
@@ -226,22 +314,291 @@ __global__ __launch_bounds__(256) void k_blk_update(BlockArgs a, int last) {
         xv[4 * g + 2] = xx.z;
         xv[4 * g + 3] = xx.w;
     }
-    if (!last) return;
+    if (last) blk_finish<VP>(a, rhs, blk, l, xv, false);
+}
+
+// y = A^{-1} z at global site gi: the two packed Hermitian blocks of the
+// site-term inverse applied to the two chiral halves
+template <int GP>
+WCL_DEV void site_inverse_apply(const BlockArgs& a, int gi, const float z[24], float y[24]) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        float c[36];
+        CloverBlk<GP>::template load<false>(a.ainv, a.g.V, gi, b, c);
+        herm6_apply(c, z + 12 * b, y + 12 * b);
+    }
+}
+
+// Block Jacobi step (the diagonal blocks of D_{Omega'} are the site terms):
+// x = x + A^{-1} (b - q) with b = rho (the projected residual, unchanged)
+// and q = D_{Omega'} x; the first step (x = 0) is x = A^{-1} b.
+template <int GP, int VP>
+__global__ __launch_bounds__(256) void k_blk_jacobi(BlockArgs a, int first, int last) {
+    const int per_rhs = a.B.nblocks * a.wpb;
+    const int rhs = blockIdx.x / per_rhs;
+    const int blk = (blockIdx.x % per_rhs) / a.wpb;
+    if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
+    const int l = (blockIdx.x % a.wpb) * 256 + threadIdx.x;
+    if (colour_skip_finish<VP>(a, rhs, blk, l, last)) return;
+    if (l >= a.B.ev) return;
+    const int e = blk * a.B.ev + l;
     int lc[4], x[4];
     block_site(a.g, a.B, blk, l, lc, x);
-    if (!block_owned(a.B, lc)) return;
     const int gi = geom_index(a.g, x);
+    float b[24], z[24], y[24], xv[24];
+    ws_load((const f4v*)a.rho + rhs * a.ws_stride, a.NE, e, b);
+    if (first) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+            z[k] = b[k];
+            xv[k] = 0.f;
+        }
+    } else {
+        float q[24];
+        ws_load((const f4v*)a.q + rhs * a.ws_stride, a.NE, e, q);
+        ws_load((const f4v*)a.x + rhs * a.ws_stride, a.NE, e, xv);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) z[k] = b[k] - q[k];
+    }
+    site_inverse_apply<GP>(a, gi, z, y);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) xv[k] += y[k];
+    if (last) blk_finish<VP>(a, rhs, blk, l, xv, false);
+    else ws_store((f4v*)a.x + rhs * a.ws_stride, a.NE, e, xv);
+}
+
+// ---- truncated BiCGStab on every domain (exactly N_dominv iterations from
+// zero, no restart, no early exit; a vanishing denominator makes its
+// coefficient zero).  Workspaces: r = rho, v = q, p = bp, s = bs, t = bt,
+// rhat = brh, x.  Per iteration five launches:
+//   p:  rho = <rhat, r>, beta = (rho/rho_old)(alpha/omega), p = r + beta (p - omega v)
+//   v = D p, partials <rhat, v>           (k_blk_dslash with dhat = rhat)
+//   s:  alpha = rho / <rhat, v>, s = r - alpha v
+//   t = D s, partials <t, s>, |t|^2        (k_blk_dslash)
+//   xr: omega = <t, s> / |t|^2, x += alpha p + omega s, r = s - omega t,
+//       partials <rhat, r>
+// Every workgroup of a domain forms the domain's scalars from the partials
+// itself (fixed order); workgroup 0 of the domain records them in dsc for
+// the later launches.
+WCL_DEV double2 cdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return double2{(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+}
+WCL_DEV double2 cmul(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+WCL_DEV bool cnz(double2 a) { return a.x != 0.0 || a.y != 0.0; }
+
+__global__ __launch_bounds__(256) void k_bcg_p(BlockArgs a, int it) {
+    const int per_rhs = a.B.nblocks * a.wpb;
+    const int rhs = blockIdx.x / per_rhs;
+    const int blk = (blockIdx.x % per_rhs) / a.wpb;
+    if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
+    if (skip_colour(a, blk)) return;
+    const int wl = blockIdx.x % a.wpb;
+    const int l = wl * 256 + threadIdx.x;
+    double* ds = a.dsc + 8 * ((size_t)rhs * a.B.nblocks + blk);
+    __shared__ float bt[4];   // beta, omega
+    if (threadIdx.x == 0) {
+        double s[3];
+        domain_sum3(a.bpart[0], a, rhs, blk, s);
+        const double2 rho{s[0], s[1]};
+        double2 beta{0.0, 0.0}, omega{0.0, 0.0};
+        if (it > 0) {
+            const double2 rho_old{ds[6], ds[7]}, alpha{ds[2], ds[3]};
+            omega = double2{ds[4], ds[5]};
+            if (cnz(rho_old) && cnz(omega)) beta = cmul(cdiv(rho, rho_old), cdiv(alpha, omega));
+        }
+        if (wl == 0) {
+            ds[0] = rho.x;
+            ds[1] = rho.y;
+        }
+        bt[0] = (float)beta.x;
+        bt[1] = (float)beta.y;
+        bt[2] = (float)omega.x;
+        bt[3] = (float)omega.y;
+    }
+    __syncthreads();
+    if (l >= a.B.ev) return;
+    const int e = blk * a.B.ev + l;
+    float r[24], p[24];
+    ws_load((const f4v*)a.rho + rhs * a.ws_stride, a.NE, e, r);
+    if (it == 0) {
+        ws_store((f4v*)a.bp + rhs * a.ws_stride, a.NE, e, r);   // p = r (p = v = 0 before)
+        return;
+    }
+    float v[24];
+    ws_load((const f4v*)a.bp + rhs * a.ws_stride, a.NE, e, p);
+    ws_load((const f4v*)a.q + rhs * a.ws_stride, a.NE, e, v);
+    const float br = bt[0], bi = bt[1], wr = bt[2], wi = bt[3];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        // u = p - omega v;  p = r + beta u
+        const float ur = p[2 * k] - (wr * v[2 * k] - wi * v[2 * k + 1]);
+        const float ui = p[2 * k + 1] - (wr * v[2 * k + 1] + wi * v[2 * k]);
+        p[2 * k] = r[2 * k] + (br * ur - bi * ui);
+        p[2 * k + 1] = r[2 * k + 1] + (br * ui + bi * ur);
+    }
+    ws_store((f4v*)a.bp + rhs * a.ws_stride, a.NE, e, p);
+}
+
+__global__ __launch_bounds__(256) void k_bcg_s(BlockArgs a) {
+    const int per_rhs = a.B.nblocks * a.wpb;
+    const int rhs = blockIdx.x / per_rhs;
+    const int blk = (blockIdx.x % per_rhs) / a.wpb;
+    if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
+    if (skip_colour(a, blk)) return;
+    const int wl = blockIdx.x % a.wpb;
+    const int l = wl * 256 + threadIdx.x;
+    double* ds = a.dsc + 8 * ((size_t)rhs * a.B.nblocks + blk);
+    __shared__ float al[2];
+    if (threadIdx.x == 0) {
+        double s[3];
+        domain_sum3(a.bpart[1], a, rhs, blk, s);
+        const double2 rv{s[0], s[1]}, rho{ds[0], ds[1]};
+        const double2 alpha = cnz(rv) ? cdiv(rho, rv) : double2{0.0, 0.0};
+        if (wl == 0) {
+            ds[2] = alpha.x;
+            ds[3] = alpha.y;
+        }
+        al[0] = (float)alpha.x;
+        al[1] = (float)alpha.y;
+    }
+    __syncthreads();
+    if (l >= a.B.ev) return;
+    const int e = blk * a.B.ev + l;
+    float r[24], v[24];
+    ws_load((const f4v*)a.rho + rhs * a.ws_stride, a.NE, e, r);
+    ws_load((const f4v*)a.q + rhs * a.ws_stride, a.NE, e, v);
+    const float ar = al[0], ai = al[1];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const float vr = v[2 * k], vi = v[2 * k + 1];
+        r[2 * k] -= ar * vr - ai * vi;
+        r[2 * k + 1] -= ar * vi + ai * vr;
+    }
+    ws_store((f4v*)a.bs + rhs * a.ws_stride, a.NE, e, r);
+}
+
+template <int VP>
+__global__ __launch_bounds__(256) void k_bcg_xr(BlockArgs a, int last) {
+    const int per_rhs = a.B.nblocks * a.wpb;
+    const int rhs = blockIdx.x / per_rhs;
+    const int blk = (blockIdx.x % per_rhs) / a.wpb;
+    if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
+    const int wl = blockIdx.x % a.wpb;
+    const int l = wl * 256 + threadIdx.x;
+    if (colour_skip_finish<VP>(a, rhs, blk, l, last)) return;
+    double* ds = a.dsc + 8 * ((size_t)rhs * a.B.nblocks + blk);
+    __shared__ float co[4];   // alpha, omega
+    if (threadIdx.x == 0) {
+        double s[3];
+        domain_sum3(a.bpart[2], a, rhs, blk, s);
+        const double2 omega = s[2] > 0.0 ? double2{s[0] / s[2], s[1] / s[2]} : double2{0.0, 0.0};
+        co[0] = (float)ds[2];
+        co[1] = (float)ds[3];
+        co[2] = (float)omega.x;
+        co[3] = (float)omega.y;
+        if (wl == 0) {
+            ds[4] = omega.x;
+            ds[5] = omega.y;
+            ds[6] = ds[0];   // rho_old = rho
+            ds[7] = ds[1];
+        }
+    }
+    __syncthreads();
+    double d[3] = {0.0, 0.0, 0.0};
+    if (l < a.B.ev) {
+        const int e = blk * a.B.ev + l;
+        const float ar = co[0], ai = co[1], wr = co[2], wi = co[3];
+        float xv[24], p[24], s[24];
+        ws_load((const f4v*)a.x + rhs * a.ws_stride, a.NE, e, xv);
+        ws_load((const f4v*)a.bp + rhs * a.ws_stride, a.NE, e, p);
+        ws_load((const f4v*)a.bs + rhs * a.ws_stride, a.NE, e, s);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            xv[2 * k] += (ar * p[2 * k] - ai * p[2 * k + 1]) + (wr * s[2 * k] - wi * s[2 * k + 1]);
+            xv[2 * k + 1] += (ar * p[2 * k + 1] + ai * p[2 * k]) + (wr * s[2 * k + 1] + wi * s[2 * k]);
+        }
+        if (last) {
+            blk_finish<VP>(a, rhs, blk, l, xv, false);
+        } else {
+            ws_store((f4v*)a.x + rhs * a.ws_stride, a.NE, e, xv);
+            float t[24], h[24];
+            ws_load((const f4v*)a.bt + rhs * a.ws_stride, a.NE, e, t);
+            ws_load((const f4v*)a.brh + rhs * a.ws_stride, a.NE, e, h);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const float tr = t[2 * k], ti = t[2 * k + 1];
+                s[2 * k] -= wr * tr - wi * ti;
+                s[2 * k + 1] -= wr * ti + wi * tr;
+            }
+            ws_store((f4v*)a.rho + rhs * a.ws_stride, a.NE, e, s);   // r = s - omega t
+            site_dot3(h, s, d);                                       // <rhat, r>
+        }
+    }
+    if (!last) block_reduce3(d, a.bpart[0] + 3 * (((size_t)rhs * a.B.nblocks + blk) * a.wpb + wl));
+}
+
+// Additive Schwarz sum: one thread per lattice site; v(x) = the sum, over
+// every domain whose extended set Omega' holds x (in each split direction
+// the own domain and, within s sites of its faces, the neighbour), of that
+// domain's extended solution at x.  Fixed order, no atomics.
+template <int VP>
+__global__ __launch_bounds__(256) void k_blk_gather(BlockArgs a) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int rhs = blockIdx.y;
+    if (i >= a.g.V) return;
+    if (a.sc && !a.sc[rhs].active) return;
+    int x[4];
+    geom_coords(a.g, i, x);
+    // per direction: the candidate domains (block coordinate, local coordinate)
+    int cb[4][3], cl[4][3], nc[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const int b = a.B.b[mu], sm = a.B.s[mu];
+        const int own = x[mu] / b, p = x[mu] - own * b;
+        int n = 0;
+        cb[mu][n] = own;
+        cl[mu][n++] = p + sm;
+        if (sm > 0 && p < sm) {   // in the upper extension of the previous domain
+            cb[mu][n] = own == 0 ? a.B.nb[mu] - 1 : own - 1;
+            cl[mu][n++] = p + sm + b;
+        }
+        if (sm > 0 && p >= b - sm) {   // in the lower extension of the next domain
+            cb[mu][n] = own == a.B.nb[mu] - 1 ? 0 : own + 1;
+            cl[mu][n++] = p + sm - b;
+        }
+        nc[mu] = n;
+    }
+    const f4v* xs = (const f4v*)a.x + rhs * a.ws_stride;
+    float v[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] = 0.f;
+    for (int i3 = 0; i3 < nc[3]; ++i3)
+        for (int i2 = 0; i2 < nc[2]; ++i2)
+            for (int i1 = 0; i1 < nc[1]; ++i1)
+                for (int i0 = 0; i0 < nc[0]; ++i0) {
+                    const int bi[4] = {i0, i1, i2, i3};
+                    int blk = 0, loc = 0;
+                    for (int mu = 3; mu >= 0; --mu) {
+                        blk = blk * a.B.nb[mu] + cb[mu][bi[mu]];
+                        loc = loc * a.B.e[mu] + cl[mu][bi[mu]];
+                    }
+                    float s[24];
+                    ws_load(xs, a.NE, blk * a.B.ev + loc, s);
+#pragma unroll
+                    for (int k = 0; k < 24; ++k) v[k] += s[k];
+                }
     char* out = (char*)a.out + rhs * a.out_stride;
     if (a.accumulate) {
         float o[24];
-        SpinorIO<WCL_F32>::load(out, a.g.V, gi, o);
+        SpinorIO<WCL_F32>::load(out, a.g.V, i, o);
 #pragma unroll
-        for (int k = 0; k < 24; ++k) o[k] += xv[k];
-        SpinorIO<WCL_F32>::store(out, a.g.V, gi, o);
+        for (int k = 0; k < 24; ++k) o[k] += v[k];
+        SpinorIO<WCL_F32>::store(out, a.g.V, i, o);
     } else {
-        SpinorIO<WCL_F32>::store(out, a.g.V, gi, xv);
+        SpinorIO<WCL_F32>::store(out, a.g.V, i, v);
     }
-    if (a.vj) SpinorIO<VP>::store((char*)a.vj + rhs * a.vj_stride, a.g.V, gi, xv);
+    if (a.vj) SpinorIO<VP>::store((char*)a.vj + rhs * a.vj_stride, a.g.V, i, v);
 }
 
 // Unpacks the extended-domain workspace q to FP64 AoS (test surface).
@@ -255,15 +612,19 @@ __global__ __launch_bounds__(256) void k_blk_unpack(BlockArgs a, const float* ws
 
 static dim3 blk_grid(const BlockArgs& a) { return dim3((unsigned)(a.B.nblocks * a.wpb * a.nrhs)); }
 
-int launch_blk_project(const BlockArgs& a, int src_prec, hipStream_t st) {
-    if (src_prec == WCL_F32) k_blk_project<WCL_F32><<<blk_grid(a), 256, 0, st>>>(a);
-    else if (src_prec == WCL_F16) k_blk_project<WCL_F16><<<blk_grid(a), 256, 0, st>>>(a);
-    else {
-        wcl_set_error("domain projection: unsupported source precision");
-        return WCL_EINVAL;
+int launch_blk_project(const BlockArgs& a, int src_prec, int bicgstab, hipStream_t st) {
+#define WCL_P(S)                                                                            \
+    if (src_prec == S) {                                                                    \
+        if (bicgstab) k_blk_project<S, true><<<blk_grid(a), 256, 0, st>>>(a);               \
+        else k_blk_project<S, false><<<blk_grid(a), 256, 0, st>>>(a);                      \
+        WCL_HIP(hipGetLastError());                                                         \
+        return WCL_OK;                                                                      \
     }
-    WCL_HIP(hipGetLastError());
-    return WCL_OK;
+    WCL_P(WCL_F32)
+    WCL_P(WCL_F16)
+#undef WCL_P
+    wcl_set_error("domain projection: unsupported source precision");
+    return WCL_EINVAL;
 }
 
 int launch_blk_dslash(const BlockArgs& a, int gp, hipStream_t st) {
@@ -280,6 +641,49 @@ int launch_blk_dslash(const BlockArgs& a, int gp, hipStream_t st) {
 int launch_blk_update(const BlockArgs& a, int vj_prec, int last, hipStream_t st) {
     if (vj_prec == WCL_F16) k_blk_update<WCL_F16><<<blk_grid(a), 256, 0, st>>>(a, last);
     else k_blk_update<WCL_F32><<<blk_grid(a), 256, 0, st>>>(a, last);
+    WCL_HIP(hipGetLastError());
+    return WCL_OK;
+}
+
+int launch_blk_jacobi(const BlockArgs& a, int gp, int vj_prec, int first, int last, hipStream_t st) {
+    if (!a.ainv) {
+        wcl_set_error("block Jacobi: site-term inverse missing");
+        return WCL_EINVAL;
+    }
+    if (gp == WCL_F32 && vj_prec == WCL_F32) k_blk_jacobi<WCL_F32, WCL_F32><<<blk_grid(a), 256, 0, st>>>(a, first, last);
+    else if (gp == WCL_F16 && vj_prec == WCL_F16)
+        k_blk_jacobi<WCL_F16, WCL_F16><<<blk_grid(a), 256, 0, st>>>(a, first, last);
+    else {
+        wcl_set_error("block Jacobi: unsupported storage precision");
+        return WCL_EINVAL;
+    }
+    WCL_HIP(hipGetLastError());
+    return WCL_OK;
+}
+
+int launch_bcg_p(const BlockArgs& a, int it, hipStream_t st) {
+    k_bcg_p<<<blk_grid(a), 256, 0, st>>>(a, it);
+    WCL_HIP(hipGetLastError());
+    return WCL_OK;
+}
+
+int launch_bcg_s(const BlockArgs& a, hipStream_t st) {
+    k_bcg_s<<<blk_grid(a), 256, 0, st>>>(a);
+    WCL_HIP(hipGetLastError());
+    return WCL_OK;
+}
+
+int launch_bcg_xr(const BlockArgs& a, int vj_prec, int last, hipStream_t st) {
+    if (vj_prec == WCL_F16) k_bcg_xr<WCL_F16><<<blk_grid(a), 256, 0, st>>>(a, last);
+    else k_bcg_xr<WCL_F32><<<blk_grid(a), 256, 0, st>>>(a, last);
+    WCL_HIP(hipGetLastError());
+    return WCL_OK;
+}
+
+int launch_blk_gather(const BlockArgs& a, int vj_prec, hipStream_t st) {
+    const dim3 grid((unsigned)((a.g.V + 255) / 256), (unsigned)a.nrhs);
+    if (vj_prec == WCL_F16) k_blk_gather<WCL_F16><<<grid, 256, 0, st>>>(a);
+    else k_blk_gather<WCL_F32><<<grid, 256, 0, st>>>(a);
     WCL_HIP(hipGetLastError());
     return WCL_OK;
 }

@@ -308,3 +308,100 @@ int launch_unpack_clover(const Geom& g, const void* c64, double* host_dev, hipSt
     WCL_HIP(hipGetLastError());
     return WCL_OK;
 }
+
+// ------------------------------------------------- site-term inverse ----
+// A(x) = 1 + csw kappa C(x) is block-diagonal in the chiral basis: two 6x6
+// Hermitian blocks.  Each block is inverted in FP64 by Gauss-Jordan
+// elimination with partial pivoting (A need not be positive definite); the
+// inverse is Hermitian and is stored packed exactly like the clover field
+// (upper triangle), so the clover loaders and herm6_apply serve it too.
+__device__ bool herm6_inverse(const double c[36], double ck, double out[36]) {
+    double m[6][6][2], v[6][6][2];
+    for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) {
+            m[a][b][0] = m[a][b][1] = 0.0;
+            v[a][b][0] = a == b ? 1.0 : 0.0;
+            v[a][b][1] = 0.0;
+        }
+    for (int a = 0; a < 6; ++a) m[a][a][0] = 1.0 + ck * c[a];
+    int k = 0;
+    for (int a = 0; a < 6; ++a)
+        for (int b = a + 1; b < 6; ++b, ++k) {
+            m[a][b][0] = ck * c[6 + 2 * k];
+            m[a][b][1] = ck * c[6 + 2 * k + 1];
+            m[b][a][0] = m[a][b][0];
+            m[b][a][1] = -m[a][b][1];
+        }
+    for (int col = 0; col < 6; ++col) {
+        int piv = col;
+        double best = m[col][col][0] * m[col][col][0] + m[col][col][1] * m[col][col][1];
+        for (int r = col + 1; r < 6; ++r) {
+            const double q = m[r][col][0] * m[r][col][0] + m[r][col][1] * m[r][col][1];
+            if (q > best) {
+                best = q;
+                piv = r;
+            }
+        }
+        if (!(best > 0.0) || !isfinite(best)) return false;
+        if (piv != col)
+            for (int j = 0; j < 6; ++j)
+                for (int z = 0; z < 2; ++z) {
+                    double t = m[col][j][z];
+                    m[col][j][z] = m[piv][j][z];
+                    m[piv][j][z] = t;
+                    t = v[col][j][z];
+                    v[col][j][z] = v[piv][j][z];
+                    v[piv][j][z] = t;
+                }
+        // row col /= pivot
+        const double pr = m[col][col][0] / best, pi = -m[col][col][1] / best;   // 1 / pivot
+        for (int j = 0; j < 6; ++j) {
+            double re = m[col][j][0] * pr - m[col][j][1] * pi, im = m[col][j][0] * pi + m[col][j][1] * pr;
+            m[col][j][0] = re;
+            m[col][j][1] = im;
+            re = v[col][j][0] * pr - v[col][j][1] * pi;
+            im = v[col][j][0] * pi + v[col][j][1] * pr;
+            v[col][j][0] = re;
+            v[col][j][1] = im;
+        }
+        for (int r = 0; r < 6; ++r) {
+            if (r == col) continue;
+            const double fr = m[r][col][0], fi = m[r][col][1];
+            for (int j = 0; j < 6; ++j) {
+                m[r][j][0] -= fr * m[col][j][0] - fi * m[col][j][1];
+                m[r][j][1] -= fr * m[col][j][1] + fi * m[col][j][0];
+                v[r][j][0] -= fr * v[col][j][0] - fi * v[col][j][1];
+                v[r][j][1] -= fr * v[col][j][1] + fi * v[col][j][0];
+            }
+        }
+    }
+    for (int a = 0; a < 6; ++a) out[a] = v[a][a][0];
+    k = 0;
+    for (int a = 0; a < 6; ++a)
+        for (int b = a + 1; b < 6; ++b, ++k) {
+            out[6 + 2 * k] = v[a][b][0];
+            out[6 + 2 * k + 1] = v[a][b][1];
+        }
+    return true;
+}
+
+__global__ __launch_bounds__(64) void k_site_inverse(Geom g, const void* c64, double ck, void* a64, void* a32, void* a16,
+                                                     int* bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.V) return;
+    double c[72], r[72];
+    CloverIO<WCL_F64>::load(c64, g.V, i, c);
+    bool ok = herm6_inverse(c, ck, r) && herm6_inverse(c + 36, ck, r + 36);
+    if (!ok) {
+        atomicOr(bad, 1);
+        for (int k = 0; k < 72; ++k) r[k] = 0.0;
+    }
+    store_clover_site(g.V, i, r, a64, a32, a16);
+}
+
+int launch_site_inverse(const Geom& g, const void* c64, double kappa, double csw, void* a64, void* a32, void* a16,
+                        int* bad, hipStream_t st) {
+    k_site_inverse<<<(g.V + 63) / 64, 64, 0, st>>>(g, c64, csw * kappa, a64, a32, a16, bad);
+    WCL_HIP(hipGetLastError());
+    return WCL_OK;
+}

@@ -173,6 +173,8 @@ struct wcl_lattice {
     void* clover[3] = {nullptr, nullptr, nullptr};
     Workspace* ws = nullptr;
     int lps = 1;   // lanes per site of the full-lattice D-apply (tunable)
+    uint64_t uid = 0;         // unique per lattice of the process (never reused)
+    uint64_t clover_gen = 0;  // incremented whenever the clover field changes
 };
 
 // device memory accounting against the context budget

@@ -102,11 +102,39 @@ struct BlockArgs {
     int nrhs;
     double* partial;     // [rhs][nblocks][wpb][3]
     const Scal* sc;      // optional: right-hand sides with sc[rhs].active == 0 are skipped
+    // split-path variants (the other readings of Sec. 1-2):
+    const void* dhat;    // k_blk_dslash: when set, the dot products are <dhat, q> and |q|^2
+                         // instead of <q, rho> and |q|^2 (truncated BiCGStab's <rhat, v>)
+    int colour;          // -1: every domain; 0 or 1: only the domains of that colour
+                         // (multiplicative Schwarz); the others write zeros at their owned sites
+    int whole;           // 1: the last step keeps the whole extended solution in x and the additive
+                         // gather sums it (overlaps add up); 0: restriction to the owned sites
+    const void* ainv;    // block Jacobi: site-term inverse A^{-1}, clover layout, storage precision
+    void* bp;            // truncated BiCGStab workspaces (float4 [rhs][6][NE]): p, s, t, rhat
+    void* bs;
+    void* bt;
+    void* brh;
+    double* bpart[3];    // truncated BiCGStab partial sums: <rhat, r>, <rhat, v>, (<t, s>, |t|^2)
+    double* dsc;         // truncated BiCGStab per-(rhs, domain) scalars [rhs][nblocks][8]:
+                         // rho, alpha, omega, rho_old (complex)
 };
 
-int launch_blk_project(const BlockArgs& a, int src_prec, hipStream_t st);
+int launch_blk_project(const BlockArgs& a, int src_prec, int bicgstab, hipStream_t st);
 int launch_blk_dslash(const BlockArgs& a, int gp, hipStream_t st);
 int launch_blk_update(const BlockArgs& a, int vj_prec, int last, hipStream_t st);
+// block Jacobi step: x = x + A^{-1} (b - q) (first: x = A^{-1} b), b = rho
+int launch_blk_jacobi(const BlockArgs& a, int gp, int vj_prec, int first, int last, hipStream_t st);
+// truncated BiCGStab: p update, s update, x/r update (see wcl_block.hip)
+int launch_bcg_p(const BlockArgs& a, int it, hipStream_t st);
+int launch_bcg_s(const BlockArgs& a, hipStream_t st);
+int launch_bcg_xr(const BlockArgs& a, int vj_prec, int last, hipStream_t st);
+// additive Schwarz: v(x) = sum of the extended solutions of every domain whose
+// Omega' holds x, out (+)= v, vj = v
+int launch_blk_gather(const BlockArgs& a, int vj_prec, hipStream_t st);
+// A^{-1} = (1 + csw kappa C)^{-1} per site, stored like the clover field in
+// FP64, FP32 and FP16; *bad (device int) is set when some A(x) is singular
+int launch_site_inverse(const Geom& g, const void* c64, double kappa, double csw, void* a64, void* a32, void* a16,
+                        int* bad, hipStream_t st);
 int launch_blk_unpack(const BlockArgs& a, const float* ws, double* out, hipStream_t st);
 // ------------------------------------------------------------- solvers --
 struct Workspace;

@@ -73,6 +73,10 @@ struct Timeline {
 struct Workspace {
     wcl_ctx* ctx = nullptr;
     Timeline tl;
+    // key of the site-term inverse held in "ainv.*" (see site_inverse)
+    uint64_t ainv_uid = 0, ainv_gen = 0;
+    double ainv_kappa = 0.0, ainv_csw = 0.0;
+    const void* ainv_ptr = nullptr;
     struct Item {
         std::string name;
         void* p;
@@ -216,6 +220,15 @@ int make_blocks(const wcl_lattice* lat, const wcl_ras_params* p, Blocks* B) {
     B->n_dominv = p->n_dominv;
     B->solver = p->block_solver;
     B->schwarz = p->schwarz;
+    // the additive sum gathers each site from its own domain and the two
+    // neighbouring ones in every direction, which covers every extended
+    // domain holding it when s <= b
+    for (int mu = 0; mu < 4; ++mu)
+        if (B->schwarz == WCL_SCHWARZ_AS && B->s[mu] > B->b[mu]) {
+            wcl_set_error("additive Schwarz needs the overlap s = %d <= the domain extent %d in direction %d",
+                          B->s[mu], B->b[mu], mu);
+            return WCL_EINVAL;
+        }
     return WCL_OK;
 }
 
@@ -229,25 +242,176 @@ static int need_fields(const wcl_lattice* lat) {
 
 // ------------------------------------------------------------------ RAS --
 // The fused (on-chip) domain solver takes extended domains of up to 256
-// sites; larger ones use the split path.
+// sites with the default readings (minimal-residual domain solves inside
+// the restricted additive iteration); every other case uses the split path.
 static int pick_kernel(const Blocks& B, int requested, bool* fused) {
     const bool fits = fused_threads(B.ev) == 256;
+    const bool variant = B.solver != WCL_DOMSOLVE_MR || B.schwarz != WCL_SCHWARZ_RAS;
     if (requested == WCL_BLOCK_FUSED && !fits) {
         wcl_set_error("fused domain solver needs an extended domain of at most 256 sites (got %d)", B.ev);
         return WCL_EINVAL;
     }
-    *fused = requested != WCL_BLOCK_SPLIT && fits;
+    if (requested == WCL_BLOCK_FUSED && variant) {
+        wcl_set_error("the fused domain solver runs minimal-residual domain solves inside RAS only; "
+                      "the other domain solvers and Schwarz iterations use the split path");
+        return WCL_EINVAL;
+    }
+    *fused = requested != WCL_BLOCK_SPLIT && fits && !variant;
     return WCL_OK;
 }
 
+// Device buffers of one Schwarz application.
+struct RasBufs {
+    void* vj[2] = {nullptr, nullptr};     // corrections v_j (storage precision)
+    void* rbuf[2] = {nullptr, nullptr};   // residuals r_j between passes (storage precision)
+    void* rho = nullptr;                  // split path: extended-domain workspaces
+    void* q = nullptr;
+    void* x = nullptr;
+    double* partial = nullptr;
+    void* bp = nullptr;                   // truncated BiCGStab
+    void* bs = nullptr;
+    void* bt = nullptr;
+    void* brh = nullptr;
+    double* bpart[3] = {nullptr, nullptr, nullptr};
+    double* dsc = nullptr;
+};
+
+struct BufReq {
+    const char* name;
+    size_t bytes;
+    void** slot;
+};
+
+static int schwarz_passes(const Blocks& B) { return B.n_ras * (B.schwarz == WCL_SCHWARZ_SAP ? 2 : 1); }
+
+// The buffers an application needs, by name.  The same list serves the
+// workspace (named, grown on demand) and any caller-provided block.
+static void ras_buffer_list(const Blocks& B, bool fused, int storage, int64_t V, int nrhs, RasBufs& b,
+                            std::vector<BufReq>& out) {
+    const size_t sst = spinor_rhs_bytes(storage, V) * nrhs;
+    out.clear();
+    if (fused) {
+        if (B.n_ras > 1) {
+            out.push_back({"ras.vj", sst, &b.vj[0]});
+            out.push_back({"ras.r0", sst, &b.rbuf[0]});
+        }
+        if (B.n_ras > 2) {
+            out.push_back({"ras.vj1", sst, &b.vj[1]});
+            out.push_back({"ras.r1", sst, &b.rbuf[1]});
+        }
+        return;
+    }
+    const int T = schwarz_passes(B);
+    const size_t NE = (size_t)B.nblocks * B.ev, wsb = (size_t)16 * 6 * NE * nrhs;
+    const int wpb = (B.ev + 255) / 256;
+    const size_t pb = (size_t)24 * nrhs * B.nblocks * wpb;
+    out.push_back({"ras.rho", wsb, &b.rho});
+    out.push_back({"ras.q", wsb, &b.q});
+    out.push_back({"ras.x", wsb, &b.x});
+    out.push_back({"ras.partial", pb, (void**)&b.partial});
+    if (T > 1) {
+        out.push_back({"ras.vj", sst, &b.vj[0]});
+        out.push_back({"ras.r0", sst, &b.rbuf[0]});
+    }
+    if (T > 2) out.push_back({"ras.r1", sst, &b.rbuf[1]});
+    if (B.solver == WCL_DOMSOLVE_BICGSTAB) {
+        out.push_back({"ras.bp", wsb, &b.bp});
+        out.push_back({"ras.bs", wsb, &b.bs});
+        out.push_back({"ras.bt", wsb, &b.bt});
+        out.push_back({"ras.brh", wsb, &b.brh});
+        out.push_back({"ras.bpart0", pb, (void**)&b.bpart[0]});
+        out.push_back({"ras.bpart1", pb, (void**)&b.bpart[1]});
+        out.push_back({"ras.bpart2", pb, (void**)&b.bpart[2]});
+        out.push_back({"ras.dsc", (size_t)64 * nrhs * B.nblocks, (void**)&b.dsc});
+    }
+}
+
+// A^{-1} = (1 + csw kappa C)^{-1} per site in FP64/FP32/FP16, built on the
+// device for (lattice, clover field, kappa, csw) and kept in the workspace
+// until one of them changes.
+static int site_inverse(wcl_lattice* lat, Workspace* ws, double kappa, double csw, hipStream_t st, void* out[3]) {
+    const int64_t V = lat->V;
+    WCL_CHECK(ws->get("ainv.f64", clover_bytes(WCL_F64, V), &out[0]));
+    WCL_CHECK(ws->get("ainv.f32", clover_bytes(WCL_F32, V), &out[1]));
+    WCL_CHECK(ws->get("ainv.f16", clover_bytes(WCL_F16, V), &out[2]));
+    if (ws->ainv_uid == lat->uid && ws->ainv_gen == lat->clover_gen && ws->ainv_kappa == kappa &&
+        ws->ainv_csw == csw && ws->ainv_ptr == out[0])
+        return WCL_OK;
+    ws->ainv_uid = 0;
+    int* bad = nullptr;
+    WCL_CHECK(ws->get("ainv.bad", 256, (void**)&bad));
+    int hbad = 0;
+    WCL_HIP(hipMemcpyAsync(bad, &hbad, sizeof(int), hipMemcpyHostToDevice, st));
+    WCL_CHECK(launch_site_inverse(lat->g, lat->clover[WCL_F64], kappa, csw, out[0], out[1], out[2], bad, st));
+    WCL_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    WCL_HIP(hipStreamSynchronize(st));
+    if (hbad) {
+        wcl_set_error("the site term 1 + c_sw kappa C(x) is singular at some site (kappa %g, c_sw %g)", kappa, csw);
+        return WCL_EINVAL;
+    }
+    ws->ainv_uid = lat->uid;
+    ws->ainv_gen = lat->clover_gen;
+    ws->ainv_kappa = kappa;
+    ws->ainv_csw = csw;
+    ws->ainv_ptr = out[0];
+    return WCL_OK;
+}
+
+static void tl_mark(Timeline* tl, int cat) {
+    if (tl) tl->mark(cat);
+}
+
+// One domain solve on the split path for the current pass: projection of
+// the source, the domain solver's iterations, and the write-out (restriction
+// to the owned sites, or the additive gather).
+static int split_domain_solve(const BlockArgs& a0, const Blocks& B, int storage, int src_prec, const RasBufs& bf,
+                              hipStream_t st) {
+    BlockArgs a = a0;
+    const int n = B.n_dominv;
+    if (B.solver == WCL_DOMSOLVE_MR) {
+        WCL_CHECK(launch_blk_project(a, src_prec, 0, st));
+        for (int k = 0; k < n; ++k) {
+            WCL_CHECK(launch_blk_dslash(a, storage, st));
+            WCL_CHECK(launch_blk_update(a, storage, k == n - 1, st));
+        }
+    } else if (B.solver == WCL_DOMSOLVE_JACOBI) {
+        WCL_CHECK(launch_blk_project(a, src_prec, 0, st));
+        BlockArgs ax = a;   // q = D_{Omega'} x
+        ax.rho = bf.x;
+        for (int k = 0; k < n; ++k) {
+            if (k > 0) WCL_CHECK(launch_blk_dslash(ax, storage, st));
+            WCL_CHECK(launch_blk_jacobi(a, storage, storage, k == 0, k == n - 1, st));
+        }
+    } else {
+        WCL_CHECK(launch_blk_project(a, src_prec, 1, st));
+        BlockArgs av = a, at = a;
+        av.rho = bf.bp;   // v = D p, partials <rhat, v>
+        av.q = bf.q;
+        av.dhat = bf.brh;
+        av.partial = bf.bpart[1];
+        at.rho = bf.bs;   // t = D s, partials <t, s>, |t|^2
+        at.q = bf.bt;
+        at.partial = bf.bpart[2];
+        for (int k = 0; k < n; ++k) {
+            WCL_CHECK(launch_bcg_p(a, k, st));
+            WCL_CHECK(launch_blk_dslash(av, storage, st));
+            WCL_CHECK(launch_bcg_s(a, st));
+            WCL_CHECK(launch_blk_dslash(at, storage, st));
+            WCL_CHECK(launch_bcg_xr(a, storage, k == n - 1, st));
+        }
+    }
+    if (B.schwarz == WCL_SCHWARZ_AS) WCL_CHECK(launch_blk_gather(a, storage, st));
+    return WCL_OK;
+}
+
+// v = K r for nrhs FP32 fields: n_ras sweeps of the Schwarz iteration
+// (Algorithm 1 for RAS; Sec. 1-2 for the additive and multiplicative ones).
 // sc (optional): device scalars of the calling solver; inactive rhs are skipped.
-static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int storage, int kernel, double kappa,
-                     double csw, const void* r, void* v, int nrhs, hipStream_t st, wcl_solve_stats* stats,
-                     const Scal* sc = nullptr) {
+static int ras_run(wcl_lattice* lat, const Blocks& B, bool fused, int storage, double kappa, double csw,
+                   const void* r, void* v, int nrhs, hipStream_t st, wcl_solve_stats* stats, const Scal* sc,
+                   const RasBufs& bf, const void* ainv, Timeline* tl) {
     const int64_t V = lat->V;
     const size_t s32 = spinor_rhs_bytes(WCL_F32, V), sst = spinor_rhs_bytes(storage, V);
-    bool fused = false;
-    WCL_CHECK(pick_kernel(B, kernel, &fused));
     const int no_overlap = B.s[0] == 0 && B.s[1] == 0 && B.s[2] == 0 && B.s[3] == 0;
     const int NE = fused ? 0 : B.nblocks * B.ev, wpb = (B.ev + 255) / 256;
     BlockArgs a{};
@@ -264,92 +428,122 @@ static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int stora
     a.out = v;
     a.out_stride = s32;
     a.sc = sc;
-    const size_t wsb = (size_t)16 * 6 * NE * nrhs;
-    if (!fused) WCL_CHECK(ws->get("ras.rho", wsb, &a.rho));
-    if (!fused) WCL_CHECK(ws->get("ras.q", wsb, &a.q));
-    if (!fused) WCL_CHECK(ws->get("ras.x", wsb, &a.x));
-    if (!fused) WCL_CHECK(ws->get("ras.partial", (size_t)24 * nrhs * B.nblocks * wpb, (void**)&a.partial));
-    // Between sweeps r_{j+1} = r_j - D v_j.  The on-chip path forms it inside
-    // the next sweep's kernel (v_j ping-pongs, since that kernel reads the
-    // neighbours' v_j while writing its own v_{j+1}); the split path runs a
-    // full-lattice D-apply with the axpy epilogue.
-    void *vj[2] = {nullptr, nullptr}, *rbuf[2] = {nullptr, nullptr};
-    if (B.n_ras > 1) {
-        WCL_CHECK(ws->get("ras.vj", sst * nrhs, &vj[0]));
-        if (fused && B.n_ras > 2) WCL_CHECK(ws->get("ras.vj1", sst * nrhs, &vj[1]));
-        WCL_CHECK(ws->get("ras.r0", sst * nrhs, &rbuf[0]));
-        if (B.n_ras > 2) WCL_CHECK(ws->get("ras.r1", sst * nrhs, &rbuf[1]));
-    }
-    for (int j = 0; j < B.n_ras; ++j) {
-        const bool last = j == B.n_ras - 1;
-        ws->tl.mark(CAT_DOMINV);
-        a.accumulate = j > 0;
-        a.vj_stride = sst;
-        // projection r_{Omega'} = P r, then N_dominv MR steps, then R + sum
-        if (fused) {
-            a.vprev = j == 0 ? nullptr : vj[(j - 1) % 2];
+    a.colour = -1;
+    a.rho = bf.rho;
+    a.q = bf.q;
+    a.x = bf.x;
+    a.partial = bf.partial;
+    a.ainv = ainv;
+    a.bp = bf.bp;
+    a.bs = bf.bs;
+    a.bt = bf.bt;
+    a.brh = bf.brh;
+    for (int k = 0; k < 3; ++k) a.bpart[k] = bf.bpart[k];
+    a.dsc = bf.dsc;
+    a.vj_stride = sst;
+    if (fused) {
+        // Between sweeps r_{j+1} = r_j - D v_j: the next sweep's kernel forms
+        // it (v_j ping-pongs, since that kernel reads the neighbours' v_j
+        // while writing its own v_{j+1}).
+        for (int j = 0; j < B.n_ras; ++j) {
+            const bool last = j == B.n_ras - 1;
+            tl_mark(tl, CAT_DOMINV);
+            a.accumulate = j > 0;
+            a.vprev = j == 0 ? nullptr : bf.vj[(j - 1) % 2];
             a.vprev_stride = sst;
             a.rout_stride = sst;
-            a.vj = last ? nullptr : vj[j % 2];
+            a.vj = last ? nullptr : bf.vj[j % 2];
             a.res_boundary = no_overlap;
             int src_prec;
             if (no_overlap) {
                 // sweep j > 0 starts from sweep j-1's final MR residual and
                 // adds the hops of D v_{j-1} that cross domain boundaries
-                a.src = j == 0 ? r : rbuf[(j - 1) % 2];
+                a.src = j == 0 ? r : bf.rbuf[(j - 1) % 2];
                 a.src_stride = j == 0 ? s32 : sst;
                 src_prec = j == 0 ? WCL_F32 : storage;
-                a.rout = last ? nullptr : rbuf[j % 2];
+                a.rout = last ? nullptr : bf.rbuf[j % 2];
             } else {
                 // sweep j reads r_{j-1} (r itself for j = 1), forms r_j
-                a.src = j <= 1 ? r : rbuf[(j - 1) % 2];
+                a.src = j <= 1 ? r : bf.rbuf[(j - 1) % 2];
                 a.src_stride = j <= 1 ? s32 : sst;
                 src_prec = j <= 1 ? WCL_F32 : storage;
-                a.rout = (j == 0 || last) ? nullptr : rbuf[j % 2];
+                a.rout = (j == 0 || last) ? nullptr : bf.rbuf[j % 2];
             }
             WCL_CHECK(launch_blk_fused(a, storage, src_prec, st));
             if (j > 0 && stats) stats->dslash_full += nrhs;
-            continue;
         }
-        const void* src = j == 0 ? r : rbuf[(j - 1) % 2];
-        const int src_prec = j == 0 ? WCL_F32 : storage;
+        if (stats) {
+            stats->ras_sweeps += B.n_ras;
+            stats->dslash_block += (int64_t)B.n_ras * B.n_dominv;
+        }
+        return WCL_OK;
+    }
+    // split path: every pass solves its domains on the current residual; a
+    // full-lattice D-apply with the axpy epilogue forms the next one
+    const int T = schwarz_passes(B), per = B.schwarz == WCL_SCHWARZ_SAP ? 2 : 1;
+    const void* src = r;
+    size_t src_stride = s32;
+    int src_prec = WCL_F32;
+    for (int pass = 0; pass < T; ++pass) {
+        const bool lastp = pass == T - 1;
+        tl_mark(tl, CAT_DOMINV);
+        a.colour = B.schwarz == WCL_SCHWARZ_SAP ? pass % per : -1;
+        a.whole = B.schwarz == WCL_SCHWARZ_AS;
+        a.accumulate = pass > 0;
+        a.vj = lastp ? nullptr : bf.vj[0];
         a.src = src;
-        a.src_stride = j == 0 ? s32 : sst;
-        a.vj = last ? nullptr : vj[0];
-        {
-            WCL_CHECK(launch_blk_project(a, src_prec, st));
-            for (int k = 0; k < B.n_dominv; ++k) {
-                WCL_CHECK(launch_blk_dslash(a, storage, st));
-                WCL_CHECK(launch_blk_update(a, storage, k == B.n_dominv - 1, st));
-            }
-        }
-        if (!last) {
-            // r_{j+1} = r_j - D v_j
-            DslashArgs d{};
-            d.g = lat->g;
-            d.gauge = lat->gauge[storage];
-            d.clover = lat->clover[storage];
-            d.in = vj[0];
-            d.in_stride = sst;
-            d.y = src;
-            d.y_stride = a.src_stride;
-            d.out = rbuf[j % 2];
-            d.out_stride = sst;
-            d.kappa = kappa;
-            d.csw = csw;
-            d.nrhs = nrhs;
-            d.lps = lat->lps;
-            d.sc = sc;
-            ws->tl.mark(CAT_DSLASH);
-            WCL_CHECK(launch_dslash(d, storage, storage, storage, DS_AXPY, src_prec, st));
-            if (stats) stats->dslash_full += nrhs;
-        }
+        a.src_stride = src_stride;
+        WCL_CHECK(split_domain_solve(a, B, storage, src_prec, bf, st));
+        if (lastp) break;
+        // r_{pass+1} = r_pass - D v_pass
+        DslashArgs d{};
+        d.g = lat->g;
+        d.gauge = lat->gauge[storage];
+        d.clover = lat->clover[storage];
+        d.in = bf.vj[0];
+        d.in_stride = sst;
+        d.y = src;
+        d.y_stride = src_stride;
+        d.out = bf.rbuf[pass % 2];
+        d.out_stride = sst;
+        d.kappa = kappa;
+        d.csw = csw;
+        d.nrhs = nrhs;
+        d.lps = lat->lps;
+        d.sc = sc;
+        tl_mark(tl, CAT_DSLASH);
+        WCL_CHECK(launch_dslash(d, storage, storage, storage, DS_AXPY, src_prec, st));
+        if (stats) stats->dslash_full += nrhs;
+        src = bf.rbuf[pass % 2];
+        src_stride = sst;
+        src_prec = storage;
     }
     if (stats) {
+        const int per_pass = B.solver == WCL_DOMSOLVE_MR ? B.n_dominv
+                             : B.solver == WCL_DOMSOLVE_JACOBI ? B.n_dominv - 1 : 2 * B.n_dominv;
         stats->ras_sweeps += B.n_ras;
-        stats->dslash_block += (int64_t)B.n_ras * B.n_dominv;
+        stats->dslash_block += (int64_t)T * per_pass;
     }
     return WCL_OK;
+}
+
+// sc (optional): device scalars of the calling solver; inactive rhs are skipped.
+static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int storage, int kernel, double kappa,
+                     double csw, const void* r, void* v, int nrhs, hipStream_t st, wcl_solve_stats* stats,
+                     const Scal* sc = nullptr) {
+    bool fused = false;
+    WCL_CHECK(pick_kernel(B, kernel, &fused));
+    RasBufs bf;
+    std::vector<BufReq> req;
+    ras_buffer_list(B, fused, storage, lat->V, nrhs, bf, req);
+    for (auto& q : req) WCL_CHECK(ws->get(q.name, q.bytes, q.slot));
+    void* ainv = nullptr;
+    if (!fused && B.solver == WCL_DOMSOLVE_JACOBI) {
+        void* inv[3];
+        WCL_CHECK(site_inverse(lat, ws, kappa, csw, st, inv));
+        ainv = inv[storage];
+    }
+    return ras_run(lat, B, fused, storage, kappa, csw, r, v, nrhs, st, stats, sc, bf, ainv, &ws->tl);
 }
 
 // ------------------------------------------------------------- BiCGStab --
@@ -809,6 +1003,7 @@ int wcl_apply_D_blocks(wcl_lattice* lat, const wcl_ras_params* ras, double kappa
     BlockArgs a{};
     a.g = lat->g;
     a.B = B;
+    a.colour = -1;
     a.gauge = lat->gauge[ras->storage];
     a.clover = lat->clover[ras->storage];
     a.NE = B.nblocks * B.ev;
@@ -827,7 +1022,7 @@ int wcl_apply_D_blocks(wcl_lattice* lat, const wcl_ras_params* ras, double kappa
     void* stage = nullptr;
     const size_t ob = (size_t)a.NE * 24 * sizeof(double);
     WCL_CHECK(ws->get("blocks.out", ob, &stage));
-    WCL_CHECK(launch_blk_project(a, WCL_F32, st));
+    WCL_CHECK(launch_blk_project(a, WCL_F32, 0, st));
     WCL_CHECK(launch_blk_dslash(a, ras->storage, st));
     WCL_CHECK(launch_blk_unpack(a, (const float*)a.q, (double*)stage, st));
     WCL_HIP(hipMemcpyAsync(out_host, stage, ob, hipMemcpyDeviceToHost, st));
