@@ -230,6 +230,23 @@ int wcl_block_info(const wcl_lattice* lat, const wcl_ras_params* ras, int64_t* n
 int wcl_ras_precondition(wcl_lattice* lat, const wcl_ras_params* ras, double kappa, double csw, const void* r_dev,
                          void* v_dev, int nrhs, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * v = K_RAS r as wcl_ras_precondition, with the same kernels and bitwise the
+ * same result, but its sweep buffers come from a fixed device array of
+ * WCL_NOALLOC_SCRATCH_BYTES per GPU (looked up in wcl_init; held until the
+ * process ends) and it calls no allocator.  Only the on-chip path: minimal-
+ * residual domain solves inside RAS (block_solver = MR, schwarz = RAS,
+ * kernel != SPLIT) with extended domains of at most 256 sites; anything else,
+ * or needing more than the fixed size (4 storage-precision fields x nrhs for
+ * n_ras >= 3), returns WCL_EINVAL.  Every call on one GPU shares that array,
+ * which keeps the last call's contents (nothing in it needs to start at
+ * zero): calls that overlap in time on one GPU (other streams or threads)
+ * race and must be serialised by the caller.  Asynchronous on stream. */
+#define WCL_NOALLOC_SCRATCH_BYTES (64u << 20)
+int wcl_ras_precondition_noalloc(wcl_lattice* lat, const wcl_ras_params* ras, double kappa, double csw,
+                                 const void* r_dev, void* v_dev, int nrhs, void* stream);
+
 /* ---- solvers ---- */
 
 /* Mixed-precision nested BiCGStab (Sec. 3) for nrhs FP64 fields:

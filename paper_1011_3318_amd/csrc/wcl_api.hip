@@ -91,6 +91,11 @@ int wcl_init(int device, uint64_t hbm_budget_bytes, wcl_ctx** out) {
     c->in_use = 0;
     c->arch_major = prop.major;
     c->num_cu = prop.multiProcessorCount;
+    const int rc = static_scratch_setup(device, &c->scratch);
+    if (rc != WCL_OK) {
+        delete c;
+        return rc;
+    }
     *out = c;
     return WCL_OK;
 }

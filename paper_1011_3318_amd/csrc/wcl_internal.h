@@ -160,6 +160,7 @@ struct wcl_ctx {
     int arch_major;
     int num_cu;
     std::mutex mu;   // guards in_use (serving slots allocate concurrently)
+    void* scratch = nullptr;   // this device's fixed scratch block (see static_scratch_setup)
 };
 
 struct Workspace;  // solver scratch, defined in wcl_solver.hip
@@ -184,3 +185,6 @@ void wcl_dev_free(wcl_ctx* ctx, void* p, size_t bytes);
 int check_prec(int prec);
 void wcl_free_workspace(wcl_lattice* lat);  // solver workspace, wcl_solver.hip
 int make_blocks(const wcl_lattice* lat, const wcl_ras_params* p, Blocks* B);
+// Device address of the fixed scratch block on `device` (current), looked up
+// once per device (wcl_solver.hip).
+int static_scratch_setup(int device, void** ptr);

@@ -12,6 +12,7 @@
 // iteration for the convergence decision.
 #include <cmath>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -285,7 +286,8 @@ struct BufReq {
 static int schwarz_passes(const Blocks& B) { return B.n_ras * (B.schwarz == WCL_SCHWARZ_SAP ? 2 : 1); }
 
 // The buffers an application needs, by name.  The same list serves the
-// workspace (named, grown on demand) and any caller-provided block.
+// workspace (named, grown on demand) and the fixed scratch block of the
+// no-allocation entry point.
 static void ras_buffer_list(const Blocks& B, bool fused, int storage, int64_t V, int nrhs, RasBufs& b,
                             std::vector<BufReq>& out) {
     const size_t sst = spinor_rhs_bytes(storage, V) * nrhs;
@@ -544,6 +546,31 @@ static int ras_apply(wcl_lattice* lat, Workspace* ws, const Blocks& B, int stora
         ainv = inv[storage];
     }
     return ras_run(lat, B, fused, storage, kappa, csw, r, v, nrhs, st, stats, sc, bf, ainv, &ws->tl);
+}
+
+// ------------------------------------------------- fixed scratch block --
+// For callers that cannot allocate (graph capture, tight serving loops):
+// the on-chip path's sweep buffers come from this fixed device array
+// instead of the workspace.  Each device holds its own copy at its own
+// address, looked up once per device when a context opens on it.
+static __device__ __align__(256) unsigned char scratch[WCL_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {};
+
+int static_scratch_setup(int device, void** ptr) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= 64) {
+        wcl_set_error("device %d out of range for the fixed scratch block", device);
+        return WCL_EINVAL;
+    }
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        WCL_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return WCL_OK;
 }
 
 // ------------------------------------------------------------- BiCGStab --
@@ -1042,6 +1069,45 @@ int wcl_ras_precondition(wcl_lattice* lat, const wcl_ras_params* ras, double kap
     WCL_HIP(hipSetDevice(lat->ctx->device));
     return ras_apply(lat, lattice_ws(lat), B, ras->storage, ras->kernel, kappa, csw, r_dev, v_dev, nrhs, (hipStream_t)stream,
                      nullptr);
+}
+
+int wcl_ras_precondition_noalloc(wcl_lattice* lat, const wcl_ras_params* ras, double kappa, double csw,
+                                 const void* r_dev, void* v_dev, int nrhs, void* stream) {
+    if (!lat || !ras || !r_dev || !v_dev || r_dev == v_dev || nrhs < 1) {
+        wcl_set_error("wcl_ras_precondition_noalloc: bad argument");
+        return WCL_EINVAL;
+    }
+    WCL_CHECK(need_fields(lat));
+    Blocks B;
+    WCL_CHECK(make_blocks(lat, ras, &B));
+    if (B.solver != WCL_DOMSOLVE_MR || B.schwarz != WCL_SCHWARZ_RAS || ras->kernel == WCL_BLOCK_SPLIT ||
+        fused_threads(B.ev) != 256) {
+        wcl_set_error("wcl_ras_precondition_noalloc: only the on-chip path (minimal-residual domain solves inside "
+                      "RAS, extended domains of at most 256 sites) runs without allocating");
+        return WCL_EINVAL;
+    }
+    if (!lat->ctx->scratch) {
+        wcl_set_error("wcl_ras_precondition_noalloc: fixed scratch block not set up on device %d", lat->ctx->device);
+        return WCL_ESTATE;
+    }
+    RasBufs bf;
+    std::vector<BufReq> req;
+    ras_buffer_list(B, true, ras->storage, lat->V, nrhs, bf, req);
+    size_t off = 0;
+    for (auto& q : req) off += round_up(q.bytes, 256);
+    if (off > (size_t)WCL_NOALLOC_SCRATCH_BYTES) {
+        wcl_set_error("wcl_ras_precondition_noalloc: needs %zu bytes of scratch for %d rhs on this lattice, "
+                      "more than the fixed %zu", off, nrhs, (size_t)WCL_NOALLOC_SCRATCH_BYTES);
+        return WCL_EINVAL;
+    }
+    off = 0;
+    for (auto& q : req) {
+        *q.slot = (char*)lat->ctx->scratch + off;
+        off += round_up(q.bytes, 256);
+    }
+    WCL_HIP(hipSetDevice(lat->ctx->device));
+    return ras_run(lat, B, true, ras->storage, kappa, csw, r_dev, v_dev, nrhs, (hipStream_t)stream, nullptr, nullptr,
+                   bf, nullptr, nullptr);
 }
 
 int wcl_solve_nested_bicgstab(wcl_lattice* lat, const wcl_solver_params* p, double kappa, double csw,

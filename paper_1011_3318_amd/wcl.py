@@ -92,6 +92,7 @@ def _load():
         "wcl_apply_D_blocks": (i, [vp, C.POINTER(RasParams), d, d, vp, dp, vp]),
         "wcl_block_info": (i, [vp, C.POINTER(RasParams), C.POINTER(i64), C.POINTER(i64)]),
         "wcl_ras_precondition": (i, [vp, C.POINTER(RasParams), d, d, vp, vp, i, vp]),
+        "wcl_ras_precondition_noalloc": (i, [vp, C.POINTER(RasParams), d, d, vp, vp, i, vp]),
         "wcl_solve_nested_bicgstab": (i, [vp, C.POINTER(SolverParams), d, d, vp, vp, i, C.POINTER(SolveStats), vp]),
         "wcl_solve_bicgstab_f64": (i, [vp, d, i, d, d, vp, vp, C.POINTER(SolveStats), vp]),
     }
@@ -220,6 +221,12 @@ class Lattice:
     def ras_precondition(self, ras: RasParams, kappa, csw, r: torch.Tensor, v: torch.Tensor, nrhs: int = 1,
                          stream=None):
         check(lib.wcl_ras_precondition(self.h, C.byref(ras), kappa, csw, _ptr(r), _ptr(v), nrhs, _stream(stream)))
+        return v
+
+    def ras_precondition_noalloc(self, ras: RasParams, kappa, csw, r: torch.Tensor, v: torch.Tensor, nrhs: int = 1,
+                                 stream=None):
+        check(lib.wcl_ras_precondition_noalloc(self.h, C.byref(ras), kappa, csw, _ptr(r), _ptr(v), nrhs,
+                                               _stream(stream)))
         return v
 
     # ---- solvers
