@@ -128,7 +128,9 @@ typedef struct wcl_solver_params {
     int max_restarts;
     int precond;            /* WCL_PRECOND_* */
     wcl_ras_params ras;
-    int even_odd;           /* 1: solve the even-odd reduced system (precond must be NONE); 0: the full D */
+    int even_odd;           /* 1: both solver levels work on the even-odd reduced system Dhat phi_e = b_e
+                               (see wcl_apply_schur; precond must be NONE, every extent even), phi_o is
+                               reconstructed, and the true residual reported is that of the full D */
     int timers;             /* 1: per-category HIP-event times into wcl_solve_stats (ms_dslash, ...) */
 } wcl_solver_params;
 
@@ -208,6 +210,18 @@ int wcl_unpack_spinor_dev(wcl_lattice* lat, int prec, int nrhs, const void* dev_
  * FP64 for WCL_F64, FP32 otherwise).  in and out must not alias. */
 int wcl_apply_D(wcl_lattice* lat, int prec, double kappa, double csw, const void* in_dev, void* out_dev, int nrhs,
                 void* stream);
+
+/* Even-odd reduced operator (not in the paper; an accelerator of the same
+ * solve): with H the hopping part of D and the sites split by parity
+ * (x+y+z+t mod 2; every extent must be even, else WCL_EINVAL),
+ *   out_e = Dhat in_e = A_ee in_e - H_eo A_oo^{-1} H_oe in_e,  out_o = 0,
+ * A = 1 + c_SW kappa C the site term, inverted per site (two 6x6 Hermitian
+ * blocks, built once per (kappa, c_SW); WCL_EINVAL if singular).  in and out
+ * are full-lattice fields of nrhs right-hand sides in the internal layout at
+ * prec = WCL_F64 or WCL_F32 (the odd sites of in are not read); they must
+ * not alias.  May allocate workspace on first use. */
+int wcl_apply_schur(wcl_lattice* lat, int prec, double kappa, double csw, const void* in_dev, void* out_dev, int nrhs,
+                    void* stream);
 
 /* Domain operator test surface (Sec. 2): for every domain i,
  * out_i = D_{Omega'_i} P_{Omega'_i} in, D_{Omega'} being the principal

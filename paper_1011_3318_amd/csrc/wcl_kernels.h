@@ -40,6 +40,32 @@ int launch_unpack_clover(const Geom& g, const void* c64, double* host_dev, hipSt
 int dslash_partials_per_rhs(int V, int lps);
 int launch_dslash(const DslashArgs& a, int gp, int spi, int spo, int epi, int spy, hipStream_t st);
 
+// --------------------------------------------------------- even-odd ----
+// Steps of the even-odd reduction (wcl_evenodd.hip); "half" fields hold the
+// V/2 sites of one parity, the site of parity p in pair (2h, 2h+1) at index h.
+enum { EO_INV = 0, EO_SCHUR = 1, EO_PREP = 2, EO_RECON = 3, EO_SITEINV = 4, EO_EXTRACT = 5, EO_INSERT = 6,
+       EO_ZERO = 7 };
+struct EoArgs {
+    Geom g;
+    int Vh;              // V / 2
+    int parity;          // parity of the sites the launch computes
+    const void* gauge;   // full-lattice fields, precision of the launch
+    const void* clover;
+    const void* ainv;    // site-term inverse, clover layout
+    const void* in;      // half field of the other parity (hop source)
+    const void* in2;     // half field of `parity` (EO_SCHUR site-term operand, EO_INSERT source)
+    const void* y;       // full field (EO_PREP/RECON/SITEINV/EXTRACT) or half field (EO_SCHUR axpy)
+    const void* a;       // half field: left vector of the DS_DOT partials
+    void* out;           // half field, or full field for EO_RECON/INSERT/ZERO
+    size_t in_stride, in2_stride, y_stride, a_stride, out_stride;   // bytes per rhs
+    double kappa, csw;
+    int nrhs;
+    double* partial;     // DS_DOT: [nrhs][tiles][3]
+    const Scal* sc;      // optional: right-hand sides with sc[rhs].active == 0 are skipped
+};
+int eo_partials_per_rhs(int Vh);
+int launch_eo(const EoArgs& a, int prec, int mode, int epi, hipStream_t st);
+
 // ------------------------------------------------------------- solvers --
 enum { FIN_RHO = 2, FIN_PP = 3, FIN_RR = 4, FIN_RR0 = 5 };
 

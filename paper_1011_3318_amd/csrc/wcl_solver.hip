@@ -160,13 +160,19 @@ void workspace_get(Workspace* w, const char* name, size_t bytes, void** out, int
 size_t nested_workspace_bytes(const wcl_lattice* lat, const wcl_solver_params* prm, int nrhs) {
     const size_t v64 = spinor_rhs_bytes(WCL_F64, lat->V) * nrhs, v32 = spinor_rhs_bytes(WCL_F32, lat->V) * nrhs;
     size_t b = 8 * v64 + 10 * v32;   // outer and inner BiCGStab vectors, inner rhs/solution
+    const size_t ainv = clover_bytes(WCL_F64, lat->V) + clover_bytes(WCL_F32, lat->V) + clover_bytes(WCL_F16, lat->V);
     if (prm && prm->precond == WCL_PRECOND_RAS) {
         Blocks B;
         if (make_blocks(lat, &prm->ras, &B) == WCL_OK) {
             b += 4 * spinor_rhs_bytes(prm->ras.storage, lat->V) * nrhs;   // v_j, r_j ping-pong
-            if (fused_threads(B.ev) != 256) b += (size_t)3 * 96 * B.nblocks * B.ev * nrhs;   // split workspaces
+            const bool split = fused_threads(B.ev) != 256 || B.solver != WCL_DOMSOLVE_MR ||
+                               B.schwarz != WCL_SCHWARZ_RAS;
+            const int nws = B.solver == WCL_DOMSOLVE_BICGSTAB ? 7 : 3;
+            if (split) b += (size_t)nws * 96 * B.nblocks * B.ev * nrhs;   // split workspaces
+            if (B.solver == WCL_DOMSOLVE_JACOBI) b += ainv;
         }
     }
+    if (prm && prm->even_odd) b += ainv + 5 * v64;   // site-term inverse, half fields, full residual
     const size_t partials = (size_t)24 * nrhs * ((lat->V + 63) / 64);
     return b + 6 * partials + (1 << 20);
 }
@@ -606,17 +612,23 @@ struct Engine {
     Scal* h;      // pinned host mirror
     Scal* hmap;   // h as the device addresses it (written by the finalize kernels)
     hipEvent_t ev = nullptr;   // recorded after each iteration's last finalize
+    // even-odd: the operator is the Schur complement Dhat on the even half
+    // fields (vectors of V/2 sites); eo_ainv = site-term inverse at precision P
+    int eo = 0;
+    const void* eo_ainv = nullptr;
+    void* eo_t = nullptr;   // half-field temporary A_oo^{-1} H_oe x
 
     ~Engine() {
         if (ev) (void)hipEventDestroy(ev);
     }
 
     int init(const Precond* K) {
-        V = lat->V;
+        V = eo ? lat->V / 2 : lat->V;
         vb = spinor_rhs_bytes(P, V) * nrhs;
         Gb = blas_partials(P, V);
-        Gd = dslash_partials_per_rhs((int)V, lat->lps);
+        Gd = eo ? eo_partials_per_rhs((int)V) : dslash_partials_per_rhs((int)V, lat->lps);
         auto name = [&](const char* n) { return tag + "." + n; };
+        if (eo) WCL_CHECK(ws->get(name("eot"), vb, &eo_t));
         WCL_CHECK(ws->get(name("r"), vb, &r));
         WCL_CHECK(ws->get(name("rh"), vb, &rh));
         WCL_CHECK(ws->get(name("p"), vb, &p));
@@ -636,7 +648,37 @@ struct Engine {
         if (!ev) WCL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         return WCL_OK;
     }
+    // Dhat x in two launches: eo_t = A_oo^{-1} H_oe x (odd sites), then
+    // out = A_ee x - H_eo eo_t (even sites) with the epilogue epi
+    int apply_schur(const void* in, void* out, const void* a, const void* y, int epi) {
+        EoArgs e{};
+        e.g = lat->g;
+        e.Vh = (int)V;
+        e.gauge = lat->gauge[gp];
+        e.clover = lat->clover[gp];
+        e.ainv = eo_ainv;
+        e.in_stride = e.in2_stride = e.y_stride = e.a_stride = e.out_stride = spinor_rhs_bytes(P, V);
+        e.kappa = kappa;
+        e.csw = csw;
+        e.nrhs = nrhs;
+        e.sc = d;
+        e.parity = 1;
+        e.in = in;
+        e.out = eo_t;
+        if (stats) stats->dslash_full += nrhs;
+        ws->tl.mark(CAT_DSLASH);
+        WCL_CHECK(launch_eo(e, P, EO_INV, DS_PLAIN, st));
+        e.parity = 0;
+        e.in = eo_t;
+        e.in2 = in;
+        e.out = out;
+        e.a = a;
+        e.y = y;
+        e.partial = partial;
+        return launch_eo(e, P, EO_SCHUR, epi, st);
+    }
     int apply_dot(const void* in, void* out, const void* a) {
+        if (eo) return apply_schur(in, out, a, nullptr, DS_DOT);
         DslashArgs x{};
         x.g = lat->g;
         x.gauge = lat->gauge[gp];
@@ -657,6 +699,7 @@ struct Engine {
     }
     // out = b - D x (FP64 true residual)
     int residual(const void* b, const void* x, void* out) {
+        if (eo) return apply_schur(x, out, nullptr, b, DS_AXPY);
         DslashArgs a{};
         a.g = lat->g;
         a.gauge = lat->gauge[gp];
@@ -918,8 +961,58 @@ static int check_solver_params(const wcl_solver_params* p) {
     return WCL_OK;
 }
 
+// |v_i|^2 of nrhs fields read back to the host (synchronous).
+static int host_norms2(Workspace* ws, int prec, int64_t V, int nrhs, const void* v, hipStream_t st,
+                       std::vector<double>& out) {
+    const int G = blas_partials(prec, V);
+    Scal *d = nullptr, *h = nullptr, *hm = nullptr;
+    double* part = nullptr;
+    WCL_CHECK(ws->get("norm.scal", sizeof(Scal) * nrhs, (void**)&d));
+    WCL_CHECK(ws->get("norm.partial", (size_t)24 * nrhs * G, (void**)&part));
+    WCL_CHECK(ws->host_scal("norm", nrhs, &h));
+    WCL_HIP(hipHostGetDevicePointer((void**)&hm, h, 0));
+    for (int i = 0; i < nrhs; ++i) {
+        h[i] = Scal{};
+        h[i].active = 1;
+    }
+    WCL_HIP(hipMemcpyAsync(d, h, sizeof(Scal) * nrhs, hipMemcpyHostToDevice, st));
+    WCL_CHECK(blas_dot(prec, V, nrhs, d, v, v, part, st));
+    WCL_CHECK(blas_finalize(part, G, nrhs, d, FIN_RR, st, hm));
+    WCL_HIP(hipStreamSynchronize(st));
+    out.assign(nrhs, 0.0);
+    for (int i = 0; i < nrhs; ++i) out[i] = h[i].rr;
+    return WCL_OK;
+}
+
+static EoArgs eo_args(const wcl_lattice* lat, int prec, const void* ainv, double kappa, double csw, int nrhs) {
+    EoArgs e{};
+    e.g = lat->g;
+    e.Vh = (int)(lat->V / 2);
+    e.gauge = lat->gauge[prec];
+    e.clover = lat->clover[prec];
+    e.ainv = ainv;
+    e.in_stride = e.in2_stride = e.a_stride = spinor_rhs_bytes(prec, e.Vh);
+    e.y_stride = e.out_stride = spinor_rhs_bytes(prec, lat->V);
+    e.kappa = kappa;
+    e.csw = csw;
+    e.nrhs = nrhs;
+    return e;
+}
+
+static int need_even_extents(const wcl_lattice* lat) {
+    for (int mu = 0; mu < 4; ++mu)
+        if (lat->g.L[mu] % 2) {
+            wcl_set_error("the even-odd reduction needs even extents (L[%d] = %d)", mu, lat->g.L[mu]);
+            return WCL_EINVAL;
+        }
+    return WCL_OK;
+}
+
 // The nested solve on an explicit workspace (used by the C ABI with the
 // lattice's own workspace and by the serving loop with per-slot ones).
+// even_odd: both levels solve the Schur complement Dhat phi_e = b_e on the
+// even half fields; phi_o is reconstructed afterwards and the reported true
+// residual is |eta - D phi| / |eta| of the full system.
 int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, double kappa, double csw,
                  const void* eta, void* phi, int nrhs, wcl_solve_stats* stats, hipStream_t st) {
     WCL_CHECK(check_solver_params(prm));
@@ -928,10 +1021,13 @@ int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, 
         wcl_set_error("wcl_solve_nested_bicgstab: bad argument");
         return WCL_EINVAL;
     }
+    const bool eo = prm->even_odd != 0;
+    if (eo) WCL_CHECK(need_even_extents(lat));
     Blocks B{};
     const bool use_ras = prm->precond == WCL_PRECOND_RAS;
     if (use_ras) WCL_CHECK(make_blocks(lat, &prm->ras, &B));
     const int storage = prm->ras.storage;
+    const int64_t Vs = eo ? lat->V / 2 : lat->V;   // sites of the solved system's vectors
     wcl_solve_stats local{};
     wcl_solve_stats* S = stats ? stats : &local;
     *S = wcl_solve_stats{};
@@ -946,32 +1042,109 @@ int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, 
     }
 
     Engine inner{lat, ws, "in", WCL_F32, WCL_F32, nrhs, kappa, csw, st, S};
+    Engine outer{lat, ws, "out", WCL_F64, WCL_F64, nrhs, kappa, csw, st, S};
+    // even-odd: b_e = eta_e - H_eo A_oo^{-1} eta_o, solved for x_e
+    const void* rhs_vec = eta;
+    void* sol_vec = phi;
+    double tol = prm->tol_outer;
+    std::vector<double> eta2;
+    if (eo) {
+        void* inv[3];
+        WCL_CHECK(site_inverse(lat, ws, kappa, csw, st, inv));
+        inner.eo = outer.eo = 1;
+        inner.eo_ainv = inv[WCL_F32];
+        outer.eo_ainv = inv[WCL_F64];
+        const size_t h64 = spinor_rhs_bytes(WCL_F64, Vs) * nrhs;
+        void *be = nullptr, *te = nullptr, *xe = nullptr;
+        WCL_CHECK(ws->get("eo.b", h64, &be));
+        WCL_CHECK(ws->get("eo.t", h64, &te));
+        WCL_CHECK(ws->get("eo.x", h64, &xe));
+        EoArgs e = eo_args(lat, WCL_F64, inv[WCL_F64], kappa, csw, nrhs);
+        ws->tl.mark(CAT_DSLASH);
+        e.parity = 1;   // te = A_oo^{-1} eta_o
+        e.y = eta;
+        e.out = te;
+        e.out_stride = spinor_rhs_bytes(WCL_F64, Vs);
+        WCL_CHECK(launch_eo(e, WCL_F64, EO_SITEINV, DS_PLAIN, st));
+        e.parity = 0;   // be = eta_e - H_eo te
+        e.in = te;
+        e.out = be;
+        WCL_CHECK(launch_eo(e, WCL_F64, EO_PREP, DS_PLAIN, st));
+        // The outer loop measures its residual against |b_e|; |eta - D phi|
+        // equals the even part |b_e - Dhat x_e| (the odd part is solved
+        // exactly), so it runs to tol |eta| / |b_e|.
+        std::vector<double> b2;
+        ws->tl.mark(CAT_BLAS);
+        WCL_CHECK(host_norms2(ws, WCL_F64, lat->V, nrhs, eta, st, eta2));
+        WCL_CHECK(host_norms2(ws, WCL_F64, Vs, nrhs, be, st, b2));
+        for (int i = 0; i < nrhs; ++i)
+            if (b2[i] > 0 && eta2[i] > 0) tol = std::min(tol, prm->tol_outer * std::sqrt(eta2[i] / b2[i]));
+        rhs_vec = be;
+        sol_vec = xe;
+    }
     void *b32 = nullptr, *y32 = nullptr;
-    const size_t v32 = spinor_rhs_bytes(WCL_F32, lat->V) * nrhs;
+    const size_t v32 = spinor_rhs_bytes(WCL_F32, Vs) * nrhs;
     WCL_CHECK(ws->get("nest.b32", v32, &b32));
     WCL_CHECK(ws->get("nest.y32", v32, &y32));
     Precond Kras = [&](const void* in, void* out, Scal* sc, const std::vector<int>&) -> int {
         return ras_apply(lat, ws, B, storage, prm->ras.kernel, kappa, csw, in, out, nrhs, st, S, sc);
     };
-    Engine outer{lat, ws, "out", WCL_F64, WCL_F64, nrhs, kappa, csw, st, S};
-    int outer_partials_G = blas_partials(WCL_F64, lat->V);
+    int outer_partials_G = blas_partials(WCL_F64, Vs);
     Precond Kinner = [&](const void* in, void* out, Scal* sc, const std::vector<int>& act) -> int {
         // b = in/|in| in FP32, inner solve, out = |in| y in FP64
         ws->tl.mark(CAT_BLAS);
-        WCL_CHECK(blas_dot(WCL_F64, lat->V, nrhs, sc, in, in, outer.partial, st));
+        WCL_CHECK(blas_dot(WCL_F64, Vs, nrhs, sc, in, in, outer.partial, st));
         WCL_CHECK(blas_finalize(outer.partial, outer_partials_G, nrhs, sc, FIN_PP, st));
-        WCL_CHECK(blas_to_f32_scaled(lat->V, nrhs, sc, in, b32, st));
+        WCL_CHECK(blas_to_f32_scaled(Vs, nrhs, sc, in, b32, st));
         std::vector<int> a = act;
         EngineResult r;
         WCL_CHECK(inner.run(b32, y32, prm->tol_inner, prm->max_inner, use_ras ? &Kras : nullptr, a, false, 0, &r));
         S->inner_iters += r.iters;
         ws->tl.mark(CAT_BLAS);
-        WCL_CHECK(blas_to_f64_scaled(lat->V, nrhs, sc, y32, out, st));
+        WCL_CHECK(blas_to_f64_scaled(Vs, nrhs, sc, y32, out, st));
         return WCL_OK;
     };
     std::vector<int> act(nrhs, 1);
     EngineResult res;
-    int rc = outer.run(eta, phi, prm->tol_outer, prm->max_outer, &Kinner, act, true, prm->max_restarts, &res);
+    int rc = outer.run(rhs_vec, sol_vec, tol, prm->max_outer, &Kinner, act, true, prm->max_restarts, &res);
+    if (rc == WCL_OK && eo) {
+        // phi_o = A_oo^{-1} (eta_o - H_oe x_e), phi_e = x_e; then the full
+        // system's true residual
+        void* inv[3];
+        WCL_CHECK(site_inverse(lat, ws, kappa, csw, st, inv));
+        EoArgs e = eo_args(lat, WCL_F64, inv[WCL_F64], kappa, csw, nrhs);
+        ws->tl.mark(CAT_DSLASH);
+        e.parity = 1;
+        e.in = sol_vec;
+        e.y = eta;
+        e.out = phi;
+        WCL_CHECK(launch_eo(e, WCL_F64, EO_RECON, DS_PLAIN, st));
+        e.parity = 0;
+        e.in2 = sol_vec;
+        WCL_CHECK(launch_eo(e, WCL_F64, EO_INSERT, DS_PLAIN, st));
+        void* rfull = nullptr;
+        WCL_CHECK(ws->get("eo.res", spinor_rhs_bytes(WCL_F64, lat->V) * nrhs, &rfull));
+        DslashArgs d{};
+        d.g = lat->g;
+        d.gauge = lat->gauge[WCL_F64];
+        d.clover = lat->clover[WCL_F64];
+        d.in = phi;
+        d.y = eta;
+        d.out = rfull;
+        d.in_stride = d.out_stride = d.y_stride = spinor_rhs_bytes(WCL_F64, lat->V);
+        d.kappa = kappa;
+        d.csw = csw;
+        d.nrhs = nrhs;
+        d.lps = lat->lps;
+        WCL_CHECK(launch_dslash(d, WCL_F64, WCL_F64, WCL_F64, DS_AXPY, WCL_F64, st));
+        S->dslash_full += nrhs;
+        std::vector<double> r2;
+        ws->tl.mark(CAT_BLAS);
+        WCL_CHECK(host_norms2(ws, WCL_F64, lat->V, nrhs, rfull, st, r2));
+        res.true_resid = 0.0;
+        for (int i = 0; i < nrhs; ++i)
+            if (eta2[i] > 0) res.true_resid = std::max(res.true_resid, std::sqrt(r2[i] / eta2[i]));
+    }
     WCL_HIP(hipEventRecord(e1, st));
     WCL_HIP(hipEventSynchronize(e1));
     float ms = 0;
@@ -1108,6 +1281,52 @@ int wcl_ras_precondition_noalloc(wcl_lattice* lat, const wcl_ras_params* ras, do
     WCL_HIP(hipSetDevice(lat->ctx->device));
     return ras_run(lat, B, true, ras->storage, kappa, csw, r_dev, v_dev, nrhs, (hipStream_t)stream, nullptr, nullptr,
                    bf, nullptr, nullptr);
+}
+
+int wcl_apply_schur(wcl_lattice* lat, int prec, double kappa, double csw, const void* in_dev, void* out_dev, int nrhs,
+                    void* stream) {
+    if (!lat || !in_dev || !out_dev || in_dev == out_dev || nrhs < 1 || (prec != WCL_F64 && prec != WCL_F32) ||
+        !std::isfinite(kappa) || !std::isfinite(csw)) {
+        wcl_set_error("wcl_apply_schur: bad argument");
+        return WCL_EINVAL;
+    }
+    WCL_CHECK(need_fields(lat));
+    WCL_CHECK(need_even_extents(lat));
+    WCL_HIP(hipSetDevice(lat->ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    Workspace* ws = lattice_ws(lat);
+    void* inv[3];
+    WCL_CHECK(site_inverse(lat, ws, kappa, csw, st, inv));
+    const int64_t Vh = lat->V / 2;
+    const size_t hb = spinor_rhs_bytes(prec, Vh) * nrhs;
+    void *xe = nullptr, *to = nullptr, *ye = nullptr;
+    WCL_CHECK(ws->get("schur.x", hb, &xe));
+    WCL_CHECK(ws->get("schur.t", hb, &to));
+    WCL_CHECK(ws->get("schur.y", hb, &ye));
+    EoArgs e = eo_args(lat, prec, inv[prec], kappa, csw, nrhs);
+    const size_t hs = spinor_rhs_bytes(prec, Vh), fs = spinor_rhs_bytes(prec, lat->V);
+    e.parity = 0;   // x_e = in on the even sites
+    e.y = in_dev;
+    e.out = xe;
+    e.out_stride = hs;
+    WCL_CHECK(launch_eo(e, prec, EO_EXTRACT, DS_PLAIN, st));
+    e.parity = 1;   // t_o = A_oo^{-1} H_oe x_e
+    e.in = xe;
+    e.out = to;
+    WCL_CHECK(launch_eo(e, prec, EO_INV, DS_PLAIN, st));
+    e.parity = 0;   // y_e = A_ee x_e - H_eo t_o
+    e.in = to;
+    e.in2 = xe;
+    e.out = ye;
+    WCL_CHECK(launch_eo(e, prec, EO_SCHUR, DS_PLAIN, st));
+    e.out = out_dev;
+    e.out_stride = fs;
+    e.parity = 1;
+    WCL_CHECK(launch_eo(e, prec, EO_ZERO, DS_PLAIN, st));
+    e.parity = 0;
+    e.in2 = ye;
+    WCL_CHECK(launch_eo(e, prec, EO_INSERT, DS_PLAIN, st));
+    return WCL_OK;
 }
 
 int wcl_solve_nested_bicgstab(wcl_lattice* lat, const wcl_solver_params* p, double kappa, double csw,

@@ -89,6 +89,7 @@ def _load():
         "wcl_pack_spinor_dev": (i, [vp, i, i, vp, vp, vp]),
         "wcl_unpack_spinor_dev": (i, [vp, i, i, vp, vp, vp]),
         "wcl_apply_D": (i, [vp, i, d, d, vp, vp, i, vp]),
+        "wcl_apply_schur": (i, [vp, i, d, d, vp, vp, i, vp]),
         "wcl_apply_D_blocks": (i, [vp, C.POINTER(RasParams), d, d, vp, dp, vp]),
         "wcl_block_info": (i, [vp, C.POINTER(RasParams), C.POINTER(i64), C.POINTER(i64)]),
         "wcl_ras_precondition": (i, [vp, C.POINTER(RasParams), d, d, vp, vp, i, vp]),
@@ -204,6 +205,10 @@ class Lattice:
     # ---- operators
     def apply_D(self, prec, kappa, csw, x: torch.Tensor, out: torch.Tensor, nrhs: int = 1, stream=None):
         check(lib.wcl_apply_D(self.h, prec, kappa, csw, _ptr(x), _ptr(out), nrhs, _stream(stream)))
+        return out
+
+    def apply_schur(self, prec, kappa, csw, x: torch.Tensor, out: torch.Tensor, nrhs: int = 1, stream=None):
+        check(lib.wcl_apply_schur(self.h, prec, kappa, csw, _ptr(x), _ptr(out), nrhs, _stream(stream)))
         return out
 
     def block_info(self, ras: RasParams):
