@@ -459,6 +459,51 @@ def oracle_resid(Oracle, np, dims, U, eta, sol, kappa, csw):
     return r
 
 
+SCHUR_ENTRY_BYTES_F32 = 1152   # wcl_apply_schur, per full-lattice site, FP32 (see variant_bench)
+
+
+def variant_bench(torch, W, np, Oracle, lat, dims, U, eta, e, phi, kappa, csw, tol, reps):
+    """The other readings of the domain solver and the Schwarz iteration
+    (Sec. 1-2) and the even-odd reduced solve, each as the preconditioner (or
+    operator) of the same nested solve on this lattice: time to solution,
+    iteration counts, the per-category timers, and the solution's true
+    residual recomputed by the oracle."""
+    cases = {
+        "RAS_MR_onchip": W.RasParams.make(block=(4, 4, 4, 4), s=0, n_ras=3, n_dominv=4, storage=W.F16),
+        "RAS_MR_split": W.RasParams.make(block=(4, 4, 4, 4), s=0, n_ras=3, n_dominv=4, storage=W.F16,
+                                         kernel=W.BLOCK_SPLIT),
+        "RAS_JACOBI": W.RasParams.make(block=(4, 4, 4, 4), s=0, n_ras=3, n_dominv=4, storage=W.F16,
+                                       block_solver=W.DOMSOLVE_JACOBI),
+        "RAS_BICGSTAB": W.RasParams.make(block=(4, 4, 4, 4), s=0, n_ras=2, n_dominv=2, storage=W.F16,
+                                         block_solver=W.DOMSOLVE_BICGSTAB),
+        "AS_MR_s1": W.RasParams.make(block=(4, 4, 4, 4), s=1, n_ras=1, n_dominv=4, storage=W.F16,
+                                     schwarz=W.SCHWARZ_AS),
+        "SAP_MR": W.RasParams.make(block=(4, 4, 4, 4), s=0, n_ras=2, n_dominv=4, storage=W.F16,
+                                   schwarz=W.SCHWARZ_SAP),
+        "even_odd_no_schwarz": None,
+    }
+    out = {}
+    o = Oracle(dims, U, precompute_clover=False)
+    for name, ras in cases.items():
+        if ras is None:
+            p = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=200,
+                                    precond=W.PRECOND_NONE, even_odd=1)
+        else:
+            p = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=100, ras=ras)
+        ms, sts = timed_solves(torch, lat, p, kappa, csw, e, phi, reps, 1)
+        sol = lat.unpack(phi, W.F64)
+        res = float(np.linalg.norm(eta - o.apply_D(sol, kappa, csw)) / np.linalg.norm(eta))
+        p.timers = 1
+        _, stt = lat.solve_nested(p, kappa, csw, e, phi)
+        out[name] = {"ms": round(ms, 3), "stats": stats_desc(sts[-1]), "timers": timers_desc(stt),
+                     "true_resid_by_oracle": res}
+        if ras is not None:
+            out[name]["ras"] = ras_desc(p)
+        log(f"variant {name}: {ms:.3f} ms, oracle true residual {res:.2e}")
+    del o
+    return out
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -586,6 +631,27 @@ def main():
     headline = {"ms": round(ms_per_step, 3), "ras": ras_desc(tuned), "stats": stats_desc(stats[-1]),
                 "true_resid": true_res, "timers": timers_desc(st_t), "plain_f64_ms": round(plain_ms, 3),
                 "plain_f64_iters": pst["outer_iters"], "speedup_vs_plain_f64": round(plain_ms / ms_per_step, 3)}
+    # ---- the even-odd reduced system at 32^4 (no Schwarz preconditioner), and its operator
+    eo32 = None
+    if not args.no_extra:
+        peo = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=200,
+                                  precond=W.PRECOND_NONE, even_odd=1)
+        ms_eo, st_eo = timed_solves(torch, lat, peo, kappa, csw, e, phi, 2, 1)
+        sol_eo = lat.unpack(phi, W.F64)
+        x32, y32 = lat.pack(eta32, W.F32), lat.empty(W.F32)
+        for _ in range(3):
+            lat.apply_schur(W.F32, kappa, csw, x32, y32)
+        torch.cuda.synchronize()
+        us_schur = event_time_us(torch, lambda k: lat.apply_schur(W.F32, kappa, csw, x32, y32), 20)
+        del x32, y32
+        gbs = SCHUR_ENTRY_BYTES_F32 * lat.V / us_schur / 1e3
+        eo32 = {"ms": round(ms_eo, 3), "stats": stats_desc(st_eo[-1]),
+                "speedup_vs_plain_f64": round(plain_ms / ms_eo, 3),
+                "schur_apply_f32": {"us": round(us_schur, 2), "bytes_per_site": SCHUR_ENTRY_BYTES_F32,
+                                    "GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                    "note": "whole wcl_apply_schur entry point: even-site extract, A_oo^-1 H_oe, "
+                                            "Schur complement, odd-site zero fill, insert"}}
+        log(f"32^4 even-odd: {ms_eo:.3f} ms; Schur entry point {us_schur:.1f} us")
     del e, phi
     lat.close()
 
@@ -655,6 +721,12 @@ def main():
                      "stats": stats_desc(st12[-1])}
             del e12, phi12, p1, f1
             log(f"12 rhs: {ms12:.3f} ms per batch")
+        variants = None
+        if not args.no_extra:
+            from oracle import Oracle
+            variants = variant_bench(torch, W, np, Oracle, l16, small_dims, U16, eta16, e16, p16, kappa, csw, tol,
+                                     max(2, args.steps // 2))
+            c2["variants"] = variants
         del e16, et16, p16
         l16.close()
         # the 4^4 plain-method anchor (eps 0.5, kappa 0.12): launch-bound FP64 BiCGStab
@@ -786,6 +858,7 @@ def main():
         "plain_f64_iters": headline["plain_f64_iters"],
         "speedup_vs_plain_f64": headline["speedup_vs_plain_f64"],
         "solve_32x4_eps1.0_f16": c3_eps1,
+        "even_odd_32x4": eo32,
         "solve_16x16x16x32": c2,
         "multi_rhs_12": multi,
         "plain_4x4_f64": anchor4,

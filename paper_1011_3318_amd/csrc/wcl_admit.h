@@ -1,14 +1,18 @@
 // Admission policy of the serving loop, as a pure function of the server's
 // memory state, so that it can be checked on the host without a device.
 //
-// A slot keeps the workspace of its last solve.  A request can reuse it at no
-// cost when the workspace was built for the same lattice and solver
-// parameters (the solve then allocates nothing new); otherwise the slot's
-// workspace is released and the request is charged its full estimate.  When
-// that does not fit the budget, the workspaces of the other idle slots are
-// released too.  With no solve running, everything but the resident fields
-// is released, so a request that fits the budget next to the resident fields
-// (which wcl_submit checks) is always admitted: the queue cannot stall.
+// A slot keeps the workspace of its last solves; its named buffers only grow
+// (a buffer is reallocated only when a request needs it larger), and freeing
+// device memory stalls every stream of the device, so workspaces are kept
+// whenever the budget allows.  A request reuses an idle slot's workspace at
+// no charge when it was built for the same lattice and solver parameters;
+// otherwise it takes the idle slot holding the most memory and is charged
+// its full estimate (an upper bound of that workspace's growth).  Only when
+// that does not fit the budget is the chosen slot's workspace released, and
+// then the other idle slots' too.  With no solve running, everything but the
+// resident fields can be released, so a request that fits the budget next
+// to the resident fields (which wcl_submit checks) is always admitted: the
+// queue cannot stall.
 #pragma once
 
 #include <cstddef>
@@ -48,6 +52,11 @@ inline AdmitDecision admit_decide(const std::vector<AdmitSlot>& slots, size_t bu
     if (other < 0) return d;   // no idle slot
     if (reuse >= 0 && resident + held_all + reserved <= budget) {
         d.slot = reuse;
+        return d;
+    }
+    if (resident + held_all + reserved + need <= budget) {   // keep every workspace
+        d.slot = other;
+        d.charge = need;
         return d;
     }
     if (resident + held_all - slots[other].held + reserved + need <= budget) {

@@ -6,8 +6,8 @@
 // the slot's own HIP stream with the slot's own workspace, so admitted
 // requests overlap on the device.  A slot keeps its workspace between
 // requests (no device allocation on the hot path once warm); admission
-// (admit_decide in wcl_admit.h) reuses it for a request of the same lattice
-// and parameters and otherwise releases it and charges the request in full.
+// (admit_decide in wcl_admit.h) keeps every workspace while the budget
+// allows and releases idle ones only when a request would not fit.
 #include <hip/hip_runtime.h>
 
 #include <chrono>

@@ -32,6 +32,14 @@ int main() {
         CHECK(d.slot == 1 && !d.release_slot && !d.release_idle && d.charge == 0);
         std::printf("ok reuse\n");
     }
+    // another lattice, budget to spare: the idle workspace holding the most is
+    // kept (it grows by at most the charge), nothing is released
+    {
+        std::vector<AdmitSlot> s = {{false, 30 * MB, 5}, {false, 10 * MB, 7}};
+        AdmitDecision d = admit_decide(s, 200 * MB, 20 * MB, 0, 50 * MB, 9);
+        CHECK(d.slot == 0 && !d.release_slot && !d.release_idle && d.charge == 50 * MB);
+        std::printf("ok keep\n");
+    }
     // the stall that a growth-only charge allowed: two idle slots hold small
     // workspaces, a large request of another lattice arrives, nothing runs
     {
@@ -100,13 +108,13 @@ int main() {
             }
             CHECK(resident + held + reserved <= budget);
             CHECK(any_busy || queue.empty());   // nothing runs only when nothing waits
-            // one unit of work on every running solve; a finished solve's
-            // workspace holds exactly its need from now on
+            // one unit of work on every running solve; a charged solve's
+            // workspace grows by at most its charge (worst case modelled)
             for (int k = 0; k < nslots; ++k) {
                 if (!slots[k].busy) continue;
                 if (--running[k].left > 0) continue;
                 reserved -= charged[k];
-                if (charged[k]) slots[k].held = running[k].need;
+                slots[k].held += charged[k];
                 slots[k].busy = false;
                 ++done;
             }

@@ -19,5 +19,5 @@ def test_admission_policy(tmp_path):
         pytest.fail(r.stdout + r.stderr)
     out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stdout + out.stderr
-    for name in ("no-idle-slot", "reuse", "idle-release", "wait-for-running", "random-streams"):
+    for name in ("no-idle-slot", "reuse", "keep", "idle-release", "wait-for-running", "random-streams"):
         assert f"ok {name}" in out.stdout
