@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--tol-inner", type=float, default=1e-5)
     ap.add_argument("--timers", action="store_true", help="solve mode: per-category HIP-event timers")
     ap.add_argument("--point-sources", action="store_true", help="solve mode: the 12 point sources in one batch")
+    ap.add_argument("--even-odd", action="store_true",
+                    help="solve mode: the even-odd reduced system without the Schwarz preconditioner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dapply", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 12-source, 32^4 and serving sections")
@@ -73,7 +75,8 @@ def parse():
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's 32^4 x-split table")
     ap.add_argument("--no-small", action="store_true", help="skip the 16^3x32 and 4^4 sections")
     ap.add_argument("--paper-eps", type=float, default=0.3, help="paper mode: gauge-field eps")
-    ap.add_argument("--paper-scan", action="store_true", help="paper mode: add the NRAS x N_dominv scan")
+    ap.add_argument("--paper-scan", action="store_true",
+                    help="paper mode: the full NRAS 1-10 x N_dominv 1-20 scan instead of the default 4 x 4 grid")
     ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="serving: concurrent solve slots")
     return ap.parse_args()
@@ -180,13 +183,19 @@ def timed_solves(torch, lat, params, kappa, csw, e, phi, steps, warmup, nrhs=1):
     return (time.perf_counter() - t0) / steps * 1e3, stats
 
 
-def paper_table(torch, W, ctx, dims, U, eta, kappa=0.126, csw=1.0, tol=1e-14, n_ras=3, n_dominv=5, scan=False):
+PAPER_SCAN_FULL = (tuple(range(1, 11)), (1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 20))
+PAPER_SCAN_DEFAULT = ((1, 2, 3, 5), (2, 3, 5, 8))
+
+
+def paper_table(torch, W, ctx, dims, U, eta, kappa=0.126, csw=1.0, tol=1e-14, n_ras=3, n_dominv=5,
+                scan=PAPER_SCAN_DEFAULT):
     """The paper's benchmark (Sec. 5, Table 1) on one GPU: 32^4 lattice,
     kappa 0.126, c_SW 1.0, |eta - D phi|/|eta| < 1e-14, the nested solver
     without preconditioner and with RAS on the x-only split into 8 domains
     (L_x/8 x L_y x L_z x L_t) with overlap depth d = 2s = 0, 2, 4, NRAS = 3,
     N_dominv = 5.  Reports time, the full-lattice D count and the domain work;
-    with scan=True also the NRAS x N_dominv scan of d = 0."""
+    scan = (NRAS values, N_dominv values) of the d = 0 scan (the paper scanned
+    NRAS 1-10 x N_dominv 1-20), or None."""
     lat = W.Lattice(ctx, dims)
     lat.upload_gauge(U)
     e = lat.pack(eta, W.F64)
@@ -233,8 +242,8 @@ def paper_table(torch, W, ctx, dims, U, eta, kappa=0.126, csw=1.0, tol=1e-14, n_
         "ras_d4": {"total_s": 37.195, "dv_count": 416, "T_Dv_calc_s": 1.205, "T_dominv_calc_s": 6.993}}
     if scan:
         grid = {}
-        for nr in range(1, 11):
-            for nd in (1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 20):
+        for nr in scan[0]:
+            for nd in scan[1]:
                 ras = W.RasParams.make(block=xb, s=0, n_ras=nr, n_dominv=nd, storage=W.F32)
                 ms, st = run(W.SolverParams.make(ras=ras, **base))
                 grid[f"{nr}x{nd}"] = {"ms": round(ms, 3), "dv_count": st["dslash_full"],
@@ -242,7 +251,7 @@ def paper_table(torch, W, ctx, dims, U, eta, kappa=0.126, csw=1.0, tol=1e-14, n_
             log(f"scan NRAS={nr}: " + ", ".join(f"{k}: {v['ms']:.0f} ms" for k, v in grid.items()
                                                  if k.startswith(f"{nr}x")))
         best = min((k for k in grid if grid[k]["converged"]), key=lambda k: grid[k]["ms"])
-        out["scan_d0"] = {"best": best, "grid": grid}
+        out["scan_d0"] = {"nras_values": list(scan[0]), "ndominv_values": list(scan[1]), "best": best, "grid": grid}
     lat.close()
     return out
 
@@ -394,27 +403,32 @@ def residual_hop_flops(dims, ras, nblocks, ev):
 def domain_kernel_rooflines(torch, W, lat, dims, ras, eta, kappa, csw, stats, n=30):
     """The domain solver's two kernel instantiations in a solve: the first
     sweep (projection, N_dominv MR steps, restriction) and the later sweeps
-    (the same plus the residual update of the previous sweep).  One sweep is
-    timed alone with HIP events (ras_precondition, NRAS = 1); a later sweep's
-    launch is the difference of NRAS = 2 and NRAS = 1.  Returns the entry of
-    the instantiation that takes the larger share of the solve first."""
+    (the same plus the residual update of the previous sweep).  A RAS
+    application with NRAS sweeps is timed alone with HIP events on the launch
+    stream (ras_precondition, T(NRAS)).  A later sweep as it runs inside an
+    application (writing the next sweep's residual and correction) takes
+    (T(6) - T(2)) / 4: both applications end with the same last sweep.  The
+    first sweep is timed alone, T(1) (as the only sweep it writes neither).
+    Returns the entry of the instantiation that takes the larger share of the
+    solve first."""
     nb, ev = lat.block_info(ras)
     if ev > 256:
         return None, None
     r32 = lat.pack(eta, W.F32)
     v32 = lat.empty(W.F32)
-    out = {}
-    for nr in (1, 2):
+    T = {}
+    for nr in (1, 2, 6):
         p = W.RasParams.make(block=tuple(ras.block), s=ras.s, n_ras=nr, n_dominv=ras.n_dominv, storage=ras.storage,
                              kernel=W.BLOCK_FUSED)
         for _ in range(5):
             lat.ras_precondition(p, kappa, csw, r32, v32)
         torch.cuda.synchronize()
-        out[nr] = event_time_us(torch, lambda k: lat.ras_precondition(p, kappa, csw, r32, v32), n)
+        T[nr] = event_time_us(torch, lambda k: lat.ras_precondition(p, kappa, csw, r32, v32), n)
     del r32, v32
     fl0 = domain_sweep_flops(dims, ras, nb, ev)
     fl1 = fl0 + residual_hop_flops(dims, ras, nb, ev)
-    t0, t1 = out[1], out[2] - out[1]
+    t1 = (T[6] - T[2]) / 4
+    t0 = T[1]
     sweeps = stats["ras_sweeps"]
     first = sweeps / max(1, ras.n_ras)
     later = sweeps - first
@@ -424,11 +438,11 @@ def domain_kernel_rooflines(torch, W, lat, dims, ras, eta, kappa, csw, stats, n=
     res = "res2" if ras.s == 0 else "res1"
     e_first = roofline_alu(fl0 / t0 / 1e6, f"k_blk_fused<{st},res0> (first sweep: {nb} domains x {ev} sites x "
                            f"{ras.n_dominv} MR steps on chip, {fl0 / 1e9:.3f} GFLOP per launch; {first:.0f} launches "
-                           f"per solve)", t0, measured_traffic("domain_counters.json", DOMAIN_SOURCES, key, lat.V),
-                           fl0)
+                           f"per solve; duration = T(NRAS 1), the sweep alone)", t0,
+                           measured_traffic("domain_counters.json", DOMAIN_SOURCES, key, lat.V), fl0)
     e_later = roofline_alu(fl1 / t1 / 1e6, f"k_blk_fused<{st},{res}> (later sweeps: residual update of the previous "
                            f"sweep, then {ras.n_dominv} MR steps on {nb} domains x {ev} sites, {fl1 / 1e9:.3f} GFLOP "
-                           f"per launch; {later:.0f} launches per solve; duration = NRAS 2 minus NRAS 1)", t1,
+                           f"per launch; {later:.0f} launches per solve; duration = (T(NRAS 6) - T(NRAS 2)) / 4)", t1,
                            measured_traffic("domain_counters.json", DOMAIN_SOURCES, key + "_" + res, lat.V), fl1)
     e_first["share_of_solve_ms"] = round(first * t0 / 1e3, 3)
     e_later["share_of_solve_ms"] = round(later * t1 / 1e3, 3)
@@ -554,7 +568,7 @@ def main():
         return
     if args.mode == "paper":
         tab = paper_table(torch, W, ctx, big, I.random_gauge(big, args.paper_eps, 1), I.gaussian_source(big, 2),
-                          scan=args.paper_scan)
+                          scan=PAPER_SCAN_FULL if args.paper_scan else PAPER_SCAN_DEFAULT)
         tab["eps"] = args.paper_eps
         print(json.dumps({"mode": "paper", "paper_table1": tab}))
         ctx.close()
@@ -590,6 +604,9 @@ def main():
                                     timers=int(args.timers),
                                     ras=W.RasParams.make(block=block, s=args.overlap, n_ras=args.n_ras,
                                                          n_dominv=args.n_dominv, storage=storage))
+            if args.even_odd:
+                p = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=200,
+                                        timers=int(args.timers), precond=W.PRECOND_NONE, even_odd=1)
             ms, sts = timed_solves(torch, lat, p, kappa, csw, e, phi, args.steps, args.warmup, nrhs)
             print(json.dumps({"mode": "solve", "lattice": list(dims), "ms": ms, "nrhs": nrhs, "ras": ras_desc(p),
                               "stats": stats_desc(sts[-1]), "timers": timers_desc(sts[-1])}))
@@ -823,6 +840,13 @@ def main():
         if multi is not None:
             resid = [oracle_resid(Oracle, np, small_dims, U16, eta12[k], sol12[k], kappa, csw) for k in (0, 5, 11)]
             multi["true_resid_by_oracle_rhs_0_5_11"] = resid
+        if U16 is not None:
+            o16 = Oracle(small_dims, U16)
+            t0 = time.perf_counter()
+            _, inf16 = o16.bicgstab(I.gaussian_source(small_dims, 2), kappa, csw, tol=tol)
+            cpu["plain_16x16x16x32_f64"] = {"s": round(time.perf_counter() - t0, 3), "iters": inf16["iters"],
+                                            "threads": cores}
+            del o16
         if anchor4 is not None:
             d4 = (4, 4, 4, 4)
             o4 = Oracle(d4, I.random_gauge(d4, 0.5, 1))

@@ -145,7 +145,7 @@ struct SpinorIO<WCL_F16> {
             for (int j = 0; j < 8; ++j) v[j] = s[8 * g + j] * inv;
             st_nt(p + tix(g, i, 3), __builtin_convertvector(v, h8v));
         }
-        st_nt((float*)scale_ptr(base, V) + i, m);
+        ((float*)scale_ptr(base, V))[i] = m;   // cached store: the 4-byte scales of a wavefront combine into whole lines
     }
 };
 
