@@ -751,8 +751,149 @@ struct SiteFields {
         for (int k = 0; k < 12; ++k) w[k] = u[MU][k];
         reconstruct_row2(w);
     }
+    WCL_DEV void refresh() {}
+    // w = U_mu(x) h (DAG = false) or U_mu(x)^dag h
+    template <int MU, bool DAG>
+    WCL_DEV void apply(const float h[12], float w[12]) const {
+        float t[18];
+        link<MU>(t);
+        su3_apply2<DAG>(t, h, w);
+    }
     // q = A r = r + ck C r
     WCL_DEV void site_term(const float r[24], float ck, float q[24]) const { clover_term(c, r, ck, q); }
+};
+
+// FP16 storage: rows 0,1 of the links and the clover stay in registers as the
+// stored binary16 values, two per register, and enter the arithmetic through
+// mixed-precision FMAs (binary16 operand, FP32 product and sum: the same
+// values as widening them first).  Row 2 of each link is rebuilt once per
+// launch in FP32 and kept, instead of once per use.  This takes 85 registers
+// where FP32 copies of the fields take 120.
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+
+template <>
+struct SiteFields<WCL_F16> {
+    h2v u[4][6];      // rows 0,1 of U_mu(x), binary16
+    float r2[4][6];   // row 2 of U_mu(x), FP32
+    h2v c[36];        // clover blocks, binary16 of value / scale
+    float cs;         // the clover's per-site scale
+    // The first product of an FMA chain is an FMA onto this zero, which the
+    // compiler cannot see through: a plain multiply has no mixed-precision
+    // form and would widen the binary16 operand in a separate instruction.
+    float zr;
+    WCL_DEV void zero() {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                u[mu][k] = h2v{(_Float16)0.f, (_Float16)0.f};
+                r2[mu][k] = 0.f;
+            }
+#pragma unroll
+        for (int k = 0; k < 36; ++k) c[k] = h2v{(_Float16)0.f, (_Float16)0.f};
+        cs = 0.f;
+        zr = 0.f;
+        asm volatile("" : "+v"(zr));
+    }
+    // Called at the top of every MR step: the packed fields become opaque
+    // there, so the compiler cannot hoist their widening out of the step loop
+    // (which would hold all of them in FP32 registers) and feeds the binary16
+    // halves to the mixed-precision FMAs instead.
+    WCL_DEV void refresh() {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) asm volatile("" : "+v"(u[mu][k]));
+#pragma unroll
+        for (int k = 0; k < 36; ++k) asm volatile("" : "+v"(c[k]));
+    }
+    template <int MU>
+    WCL_DEV float uk(int k) const { return (float)((k & 1) ? u[MU][k >> 1].y : u[MU][k >> 1].x); }
+    WCL_DEV float ck_(int k) const { return (float)((k & 1) ? c[k >> 1].y : c[k >> 1].x); }
+    WCL_DEV void load(const BlockArgs& a, int gi) {
+        const h4v* gp = (const h4v*)a.gauge;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            float t[18];
+#pragma unroll
+            for (int g = 0; g < 3; ++g) {
+                const h4v v = gp[tix(3 * mu + g, gi, 12)];
+                u[mu][2 * g] = h2v{v.x, v.y};
+                u[mu][2 * g + 1] = h2v{v.z, v.w};
+                t[4 * g] = (float)v.x;
+                t[4 * g + 1] = (float)v.y;
+                t[4 * g + 2] = (float)v.z;
+                t[4 * g + 3] = (float)v.w;
+            }
+            reconstruct_row2(t);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) r2[mu][k] = t[12 + k];
+        }
+        const h8v* cp = (const h8v*)a.clover;
+#pragma unroll
+        for (int g = 0; g < 9; ++g) {
+            const h8v v = cp[tix(g, gi, 9)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) c[4 * g + j] = h2v{v[2 * j], v[2 * j + 1]};
+        }
+        cs = ((const float*)((const char*)a.clover + half_clover_scale_offset(a.g.V)))[gi];
+    }
+    // w = U_mu(x) h (DAG = false) or U_mu(x)^dag h
+    template <int MU, bool DAG>
+    WCL_DEV void apply(const float h[12], float w[12]) const {
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                float re = zr, im = zr;
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const int row = DAG ? b : a, col = DAG ? a : b;
+                    const float ur = row < 2 ? uk<MU>(2 * (3 * row + col)) : r2[MU][2 * col];
+                    const float uv = row < 2 ? uk<MU>(2 * (3 * row + col) + 1) : r2[MU][2 * col + 1];
+                    const float ui = DAG ? -uv : uv;
+                    const float hr = h[6 * sp + 2 * b], hi = h[6 * sp + 2 * b + 1];
+                    re = fmad(ur, hr, re);
+                    re = fmad(-ui, hi, re);
+                    im = fmad(ur, hi, im);
+                    im = fmad(ui, hr, im);
+                }
+                w[6 * sp + 2 * a] = re;
+                w[6 * sp + 2 * a + 1] = im;
+            }
+    }
+    // q = A r = r + ck C r, C = cs x (the stored binary16 blocks)
+    WCL_DEV void site_term(const float r[24], float ck, float q[24]) const {
+        const float f = ck * cs;
+#pragma unroll
+        for (int bk = 0; bk < 2; ++bk) {
+            const int o = 36 * bk;
+            const float* x = r + 12 * bk;
+            float y[12];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                y[2 * a] = fmad(ck_(o + a), x[2 * a], zr);
+                y[2 * a + 1] = fmad(ck_(o + a), x[2 * a + 1], zr);
+            }
+            int k = 0;
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+#pragma unroll
+                for (int b = a + 1; b < 6; ++b, ++k) {
+                    const float re = ck_(o + 6 + 2 * k), im = ck_(o + 6 + 2 * k + 1);
+                    y[2 * a] = fmad(re, x[2 * b], y[2 * a]);
+                    y[2 * a] = fmad(-im, x[2 * b + 1], y[2 * a]);
+                    y[2 * a + 1] = fmad(re, x[2 * b + 1], y[2 * a + 1]);
+                    y[2 * a + 1] = fmad(im, x[2 * b], y[2 * a + 1]);
+                    y[2 * b] = fmad(re, x[2 * a], y[2 * b]);
+                    y[2 * b] = fmad(im, x[2 * a + 1], y[2 * b]);
+                    y[2 * b + 1] = fmad(re, x[2 * a + 1], y[2 * b + 1]);
+                    y[2 * b + 1] = fmad(-im, x[2 * a], y[2 * b + 1]);
+                }
+#pragma unroll
+            for (int j = 0; j < 12; ++j) q[12 * bk + j] = fmad(f, y[j], x[j]);
+        }
+    }
 };
 
 #ifndef WCL_FUSED_MINWAVES
@@ -829,10 +970,13 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
     if (((K) % 2 == 0 ? nf[(K) / 2] : nb[(K) / 2]) < 0) {                                 \
         float s[24], h[12], w[12], u[18];                                                 \
         SpinorIO<VP>::load(vp, a.g.V, nbr[K], s);                                         \
-        if ((K) % 2 == 0) F.template link<(K) / 2>(u);                                    \
-        else GaugeIO<GP>::template load<false>(a.gauge, a.g.V, (K) / 2, lnk[K], u);       \
         spin_project<(K) / 2, (K) % 2 == 0>(s, h);                                        \
-        su3_apply2<(K) % 2 != 0>(u, h, w);                                                \
+        if ((K) % 2 == 0) {                                                               \
+            F.template apply<(K) / 2, false>(h, w);                                       \
+        } else {                                                                          \
+            GaugeIO<GP>::template load<false>(a.gauge, a.g.V, (K) / 2, lnk[K], u);        \
+            su3_apply2<true>(u, h, w);                                                    \
+        }                                                                                 \
         spin_accumulate<(K) / 2, (K) % 2 == 0>(w, mk * ph[K], acc);                       \
     }
             WCL_XHOP(0) WCL_XHOP(1) WCL_XHOP(2) WCL_XHOP(3) WCL_XHOP(4) WCL_XHOP(5) WCL_XHOP(6) WCL_XHOP(7)
@@ -861,10 +1005,13 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
     {                                                                                 \
         float s[24], h[12], w[12], u[18];                                             \
         SpinorIO<VP>::load(vp, a.g.V, nbr[K], s);                                     \
-        if ((K) % 2 == 0) F.template link<(K) / 2>(u);                                \
-        else GaugeIO<GP>::template load<false>(a.gauge, a.g.V, (K) / 2, lnk[K], u);   \
         spin_project<(K) / 2, (K) % 2 == 0>(s, h);                                    \
-        su3_apply2<(K) % 2 != 0>(u, h, w);                                            \
+        if ((K) % 2 == 0) {                                                           \
+            F.template apply<(K) / 2, false>(h, w);                                   \
+        } else {                                                                      \
+            GaugeIO<GP>::template load<false>(a.gauge, a.g.V, (K) / 2, lnk[K], u);    \
+            su3_apply2<true>(u, h, w);                                                \
+        }                                                                             \
         spin_accumulate<(K) / 2, (K) % 2 == 0>(w, mk * ph[K], acc);                   \
     }
             WCL_RHOP(0) WCL_RHOP(1) WCL_RHOP(2) WCL_RHOP(3) WCL_RHOP(4) WCL_RHOP(5) WCL_RHOP(6) WCL_RHOP(7)
@@ -879,15 +1026,15 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
 #pragma unroll
     for (int k = 0; k < 24; ++k) s_rho[k * NT + l] = rho[k];
     for (int step = 0; step < a.B.n_dominv; ++step) {
+        F.refresh();
         // publish the backward-hop contributions U_mu(x)^dag P+ rho(x)
         {
-            float r[24], h[12], w[12], u[18];
+            float r[24], h[12], w[12];
 #pragma unroll
             for (int k = 0; k < 24; ++k) r[k] = s_rho[k * NT + l];
 #define WCL_BWD(MU)                                                         \
     spin_project<MU, false>(r, h);                                          \
-    F.template link<MU>(u);                                                 \
-    su3_apply2<true>(u, h, w);                                              \
+    F.template apply<MU, true>(h, w);                                       \
     _Pragma("unroll") for (int k = 0; k < 12; ++k) s_bwd[(MU * 12 + k) * NT + l] = w[k];
             WCL_BWD(0) WCL_BWD(1) WCL_BWD(2) WCL_BWD(3)
 #undef WCL_BWD
@@ -902,13 +1049,12 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
             F.site_term(r, ck, q);
         }
         {
-            float s[24], h[12], w[12], u[18];
+            float s[24], h[12], w[12];
 #define WCL_HOPS(MU)                                                                            \
     if (nf[MU] >= 0) {                                                                          \
         _Pragma("unroll") for (int k = 0; k < 24; ++k) s[k] = s_rho[k * NT + nf[MU]];         \
         spin_project<MU, true>(s, h);                                                           \
-        F.template link<MU>(u);                                                                 \
-        su3_apply2<false>(u, h, w);                                                             \
+        F.template apply<MU, false>(h, w);                                                      \
         spin_accumulate<MU, true>(w, mk * phf[MU], q);                                          \
     }                                                                                           \
     if (nb[MU] >= 0) {                                                                          \
