@@ -168,8 +168,8 @@ extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, dou
     // stage 2: N_dominv x NRAS
     {
         const Cand base2 = bestc;
-        for (int nd : {2, 3, 4, 5, 6})
-            for (int nr : {1, 2, 3, 4}) {
+        for (int nd = 1; nd <= 8; ++nd)
+            for (int nr = 1; nr <= 8; ++nr) {
                 Cand c = base2;
                 c.p.ras.n_dominv = nd;
                 c.p.ras.n_ras = nr;
@@ -179,11 +179,25 @@ extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, dou
     // stage 3: inner tolerance, lanes per site of the D-apply
     {
         const Cand base3 = bestc;
-        for (double tol : {1e-2, 1e-3, 1e-4, 1e-5})
+        for (double tol : {1e-2, 1e-3, 1e-4, 1e-5, 1e-6})
             for (int lps : {1, 2}) {
                 Cand c = base3;
                 c.p.tol_inner = tol;
                 c.lps = lps;
+                consider(c);
+            }
+    }
+    // stage 4: N_dominv and NRAS once more, one step around the best, at the
+    // chosen inner tolerance (the best sweep count depends on it)
+    {
+        const Cand base4 = bestc;
+        for (int dnd = -1; dnd <= 1; ++dnd)
+            for (int dnr = -1; dnr <= 1; ++dnr) {
+                const int nd = base4.p.ras.n_dominv + dnd, nr = base4.p.ras.n_ras + dnr;
+                if ((dnd == 0 && dnr == 0) || nd < 1 || nr < 1) continue;
+                Cand c = base4;
+                c.p.ras.n_dominv = nd;
+                c.p.ras.n_ras = nr;
                 consider(c);
             }
     }
