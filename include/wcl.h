@@ -283,9 +283,10 @@ int wcl_solve_bicgstab_f64(wcl_lattice* lat, double tol, int max_iter, double ka
  * timing complete nested solves of eta on this lattice: stage 1 scans
  * domain shape {4^4, 4^3x8, 8^4} x overlap {0, 1} x storage (bit 0 of
  * storage_mask: FP32, bit 1: FP16; 0 = both); stage 2 scans N_dominv
- * 1..8 x NRAS 1..8; stage 3 the inner tolerance {1e-2, ..., 1e-6} and lanes
+ * 2..8 x NRAS 1..8; stage 3 the inner tolerance {1e-2, ..., 1e-6} and lanes
  * per site {1, 2}; stage 4 N_dominv and NRAS one step around the best at the
- * chosen tolerance.  Candidates that do not converge are skipped.  eta is a tuning source: the chosen parameters serve
+ * chosen tolerance.  Candidates that do not converge within 10 outer
+ * iterations are skipped.  eta is a tuning source: the chosen parameters serve
  * any source on this lattice.  With cache_path != NULL the result is read
  * from / appended to that JSON-lines file, keyed by device architecture,
  * dims, nrhs, kappa, c_sw and storage_mask.  *best receives the chosen

@@ -118,10 +118,16 @@ extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, dou
         wcl_workspace_delete(ws);
         return rc;
     }
-    // time = best of two complete solves (the first also warms the workspace)
-    auto measure = [&](const Cand& c, double* ms) -> bool {
+    Cand bestc = cur;
+    double bms = 1e30;
+    // time = best of two complete solves (the first also warms the workspace);
+    // a candidate that needs more than 10 outer iterations is no contender and
+    // is dropped, as is the second solve of one more than 3 x slower than the best
+    auto measure = [&](const Cand& c0, double* ms) -> bool {
         Blocks B;
-        if (make_blocks(lat, &c.p.ras, &B) != WCL_OK) return false;
+        if (make_blocks(lat, &c0.p.ras, &B) != WCL_OK) return false;
+        Cand c = c0;
+        c.p.max_outer = std::min(c.p.max_outer, 10);
         const int saved = lat->lps;
         lat->lps = c.lps;
         double t = 1e30;
@@ -131,13 +137,12 @@ extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, dou
             int r = nested_solve(lat, ws, &c.p, kappa, csw, eta_dev, phi, nrhs, &s, st);
             if (r != WCL_OK || !s.converged) ok = false;
             else t = std::min(t, s.ms_total);
+            if (ok && t > 3.0 * bms) break;
         }
         lat->lps = saved;
         *ms = t;
         return ok;
     };
-    Cand bestc = cur;
-    double bms = 1e30;
     auto consider = [&](const Cand& c) {
         double ms;
         if (measure(c, &ms) && ms < bms) {
@@ -168,7 +173,7 @@ extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, dou
     // stage 2: N_dominv x NRAS
     {
         const Cand base2 = bestc;
-        for (int nd = 1; nd <= 8; ++nd)
+        for (int nd = 2; nd <= 8; ++nd)
             for (int nr = 1; nr <= 8; ++nr) {
                 Cand c = base2;
                 c.p.ras.n_dominv = nd;
