@@ -80,6 +80,13 @@ struct SpinorIO<WCL_F64> {
             s[2 * k + 1] = v.y;
         }
     }
+    // the spinor as stored and its scale (1 here): see SpinorIO<WCL_F16>
+    using Stored = T;
+    WCL_DEV static T load_u(const void* base, int V, int i, T s[24]) {
+        load(base, V, i, s);
+        return T(1);
+    }
+    WCL_DEV static T load_s(const void* base, int V, int i, Stored s[24]) { return load_u(base, V, i, s); }
     WCL_DEV static void store(void* base, int V, int i, const T s[24]) {
         d2v* p = (d2v*)base;
 #pragma unroll
@@ -104,6 +111,12 @@ struct SpinorIO<WCL_F32> {
             s[4 * g + 3] = v.w;
         }
     }
+    using Stored = T;
+    WCL_DEV static T load_u(const void* base, int V, int i, T s[24]) {
+        load(base, V, i, s);
+        return T(1);
+    }
+    WCL_DEV static T load_s(const void* base, int V, int i, Stored s[24]) { return load_u(base, V, i, s); }
     WCL_DEV static void store(void* base, int V, int i, const T s[24]) {
         f4v* p = (f4v*)base;
 #pragma unroll
@@ -131,6 +144,31 @@ struct SpinorIO<WCL_F16> {
 #pragma unroll
             for (int j = 0; j < 8; ++j) s[8 * g + j] = v[j] * sc;
         }
+    }
+    // The stored values (value / scale) widened, without the scale, which is
+    // returned: a linear consumer applies it once to its result.
+    WCL_DEV static T load_u(const void* base, int V, int i, T s[24]) {
+        const h8v* p = (const h8v*)base;
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            f8v v = __builtin_convertvector(p[tix(g, i, 3)], f8v);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s[8 * g + j] = v[j];
+        }
+        return scale_ptr(base, V)[i];
+    }
+    // The stored binary16 values themselves (consumers widen them inside
+    // mixed-precision FMAs) and the scale.
+    using Stored = _Float16;
+    WCL_DEV static T load_s(const void* base, int V, int i, _Float16 s[24]) {
+        const h8v* p = (const h8v*)base;
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            const h8v v = p[tix(g, i, 3)];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s[8 * g + j] = v[j];
+        }
+        return scale_ptr(base, V)[i];
     }
     WCL_DEV static void store(void* base, int V, int i, const T s[24]) {
         float m = 0.f;
@@ -489,11 +527,94 @@ WCL_DEV void clover_term(const T c[72], const T s[24], T ck, T acc[24]) {
     }
 }
 
+// acc = psi + ck C psi with the FP16 clover: its 72 stored binary16 values
+// (value / scale) feed mixed-precision FMAs directly, and the per-site scale
+// joins ck.  z is an opaque zero for the heads of the FMA chains (a plain
+// multiply has no mixed-precision form and would widen first).
+template <bool NT>
+WCL_DEV void clover_site_f16(const void* base, int V, int i, const float psi[24], float ck, float z,
+                             float acc[24]) {
+    const h8v* p = (const h8v*)base;
+    h8v g[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) g[k] = ldx<NT>(p + tix(k, i, 9));
+    const float f = ck * ((const float*)((const char*)base + half_clover_scale_offset(V)))[i];
+#pragma unroll
+    for (int bk = 0; bk < 2; ++bk) {
+        const int o = 36 * bk;
+        const float* x = psi + 12 * bk;
+#define WCL_CV(k) ((float)g[(o + (k)) >> 3][(o + (k)) & 7])
+        float y[12];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            y[2 * a] = fmad(WCL_CV(a), x[2 * a], z);
+            y[2 * a + 1] = fmad(WCL_CV(a), x[2 * a + 1], z);
+        }
+        int k = 0;
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+#pragma unroll
+            for (int b = a + 1; b < 6; ++b, ++k) {
+                const float re = WCL_CV(6 + 2 * k), im = WCL_CV(6 + 2 * k + 1);
+                y[2 * a] = fmad(re, x[2 * b], y[2 * a]);
+                y[2 * a] = fmad(-im, x[2 * b + 1], y[2 * a]);
+                y[2 * a + 1] = fmad(re, x[2 * b + 1], y[2 * a + 1]);
+                y[2 * a + 1] = fmad(im, x[2 * b], y[2 * a + 1]);
+                y[2 * b] = fmad(re, x[2 * a], y[2 * b]);
+                y[2 * b] = fmad(im, x[2 * a + 1], y[2 * b]);
+                y[2 * b + 1] = fmad(re, x[2 * a + 1], y[2 * b + 1]);
+                y[2 * b + 1] = fmad(-im, x[2 * a], y[2 * b + 1]);
+            }
+#undef WCL_CV
+#pragma unroll
+        for (int j = 0; j < 12; ++j) acc[12 * bk + j] = fmad(f, y[j], x[j]);
+    }
+}
+
+// spin_project from stored binary16 values: each half-spinor component is
+// one FMA u +- l with both operands widened inside it (the same value as
+// widening first and adding).
+template <int MU, bool FWD>
+WCL_DEV void spin_project(const _Float16 s[24], float h[12]) {
+    const _Float16* u0 = s;
+    const _Float16* u1 = s + 6;
+    const _Float16* l0 = s + 12;
+    const _Float16* l1 = s + 18;
+    // an opaque +-1 keeps the compiler from turning the FMA into a widen and add
+    float sg = FWD ? 1.f : -1.f;
+    asm volatile("" : "+v"(sg));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int r = 2 * c, i = 2 * c + 1;
+        if (MU == 0) {
+            h[r] = fmad((float)l1[i], -sg, (float)u0[r]);
+            h[i] = fmad((float)l1[r], sg, (float)u0[i]);
+            h[6 + r] = fmad((float)l0[i], -sg, (float)u1[r]);
+            h[6 + i] = fmad((float)l0[r], sg, (float)u1[i]);
+        } else if (MU == 1) {
+            h[r] = fmad((float)l1[r], sg, (float)u0[r]);
+            h[i] = fmad((float)l1[i], sg, (float)u0[i]);
+            h[6 + r] = fmad((float)l0[r], -sg, (float)u1[r]);
+            h[6 + i] = fmad((float)l0[i], -sg, (float)u1[i]);
+        } else if (MU == 2) {
+            h[r] = fmad((float)l0[i], -sg, (float)u0[r]);
+            h[i] = fmad((float)l0[r], sg, (float)u0[i]);
+            h[6 + r] = fmad((float)l1[i], sg, (float)u1[r]);
+            h[6 + i] = fmad((float)l1[r], -sg, (float)u1[i]);
+        } else {
+            h[r] = fmad((float)l0[r], sg, (float)u0[r]);
+            h[i] = fmad((float)l0[i], sg, (float)u0[i]);
+            h[6 + r] = fmad((float)l1[r], sg, (float)u1[r]);
+            h[6 + i] = fmad((float)l1[i], sg, (float)u1[i]);
+        }
+    }
+}
+
 // One hop from already-loaded data: s = neighbour spinor, u = rows 0,1 of
 // the link (row 2 rebuilt here).  Forward: (1 - gamma_mu) U_mu(x) psi(x+mu);
 // backward: (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu).
-template <int MU, bool FWD, typename T>
-WCL_DEV void hop_compute(const T s[24], T u[18], T f, T acc[24]) {
+template <int MU, bool FWD, typename S, typename T>
+WCL_DEV void hop_compute(const S s[24], T u[18], T f, T acc[24]) {
     T h[12], w[12];
     reconstruct_row2(u);
     spin_project<MU, FWD>(s, h);

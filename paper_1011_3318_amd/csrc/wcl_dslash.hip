@@ -37,17 +37,19 @@ WCL_DEV void clover_site(const DslashArgs& a, const char* in, int i, T acc[24]) 
 // neighbour spinor and link of hop K (requested D hops earlier); once hop K
 // is computed the slot is refilled with hop K + D, so D - 1 hops' loads are
 // in flight while a hop is computed.
-template <int K, int D, bool NT, int GP, int SPI, typename T>
+// The spinors are held as stored with their scale in ss (1 but for FP16);
+// the hop is linear, so the scale joins the hop's factor.
+template <int K, int D, bool NT, int GP, int SPI, typename S, typename T>
 WCL_DEV void hop_chain(const DslashArgs& a, const char* in, const int nbr[8], const int lnk[8], const T ph[8], T mk,
-                       T sb[D][24], T ub[D][18], T acc[24]) {
+                       S sb[D][24], T ss[D], T ub[D][18], T acc[24]) {
     if constexpr (K < 8) {
         constexpr int slot = K % D;
-        hop_compute<K / 2, (K % 2) == 0>(sb[slot], ub[slot], mk * ph[K], acc);
+        hop_compute<K / 2, (K % 2) == 0>(sb[slot], ub[slot], mk * ph[K] * ss[slot], acc);
         if constexpr (K + D < 8) {
-            SpinorIO<SPI>::load(in, a.g.V, nbr[K + D], sb[slot]);
+            ss[slot] = SpinorIO<SPI>::load_s(in, a.g.V, nbr[K + D], sb[slot]);
             GaugeIO<GP>::template load_raw<NT>(a.gauge, a.g.V, (K + D) / 2, lnk[K + D], ub[slot]);
         }
-        hop_chain<K + 1, D, NT, GP, SPI>(a, in, nbr, lnk, ph, mk, sb, ub, acc);
+        hop_chain<K + 1, D, NT, GP, SPI>(a, in, nbr, lnk, ph, mk, sb, ss, ub, acc);
     }
 }
 
@@ -60,14 +62,15 @@ WCL_DEV void dslash_site(const DslashArgs& a, const char* in, int i, T acc[24]) 
     T ph[8];
     geom_coords(a.g, i, x);
     hop_sites(a.g, i, x, nbr, lnk, ph);
-    T sb[D][24], ub[D][18];
+    typename SpinorIO<SPI>::Stored sb[D][24];
+    T ss[D], ub[D][18];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        SpinorIO<SPI>::load(in, a.g.V, nbr[k], sb[k]);
+        ss[k] = SpinorIO<SPI>::load_s(in, a.g.V, nbr[k], sb[k]);
         GaugeIO<GP>::template load_raw<NT>(a.gauge, a.g.V, k / 2, lnk[k], ub[k]);
     }
     clover_site<NT, GP, SPI>(a, in, i, acc);
-    hop_chain<0, D, NT, GP, SPI>(a, in, nbr, lnk, ph, T(-a.kappa), sb, ub, acc);
+    hop_chain<0, D, NT, GP, SPI>(a, in, nbr, lnk, ph, T(-a.kappa), sb, ss, ub, acc);
 }
 
 template <int GP, int SPI, int SPO, int EPI, int SPY, bool NT>
@@ -204,7 +207,12 @@ __global__ __launch_bounds__(256, WCL_XY_MINWAVES) void k_dslash_xy(DslashArgs a
     WCL_PHASE();
 
     T acc[24];
-    {
+    if constexpr (GP == WCL_F16) {
+        float z = 0.f;
+        asm volatile("" : "+v"(z));
+        clover_site_f16<NT>(a.clover, V, i, psi, (float)(a.csw * a.kappa), z, acc);
+        WCL_PHASE();
+    } else {
         const T ck = T(a.csw * a.kappa);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
@@ -256,14 +264,15 @@ __global__ __launch_bounds__(256, WCL_XY_MINWAVES) void k_dslash_xy(DslashArgs a
     WCL_PHASE();
     // z and t hops: the pipelined neighbour loads of k_dslash
     constexpr int D = WCL_PIPE_DEPTH;
-    T sb[D][24], ub[D][18];
+    typename SpinorIO<SPI>::Stored sb[D][24];
+    T ss[D], ub[D][18];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        SpinorIO<SPI>::load(in, V, nbr[4 + k], sb[(4 + k) % D]);
+        ss[(4 + k) % D] = SpinorIO<SPI>::load_s(in, V, nbr[4 + k], sb[(4 + k) % D]);
         GaugeIO<GP>::template load_raw<NT>(a.gauge, V, (4 + k) / 2, lnk[4 + k], ub[(4 + k) % D]);
     }
 
-    hop_chain<4, D, NT, GP, SPI>(a, in, nbr, lnk, ph, mk, sb, ub, acc);
+    hop_chain<4, D, NT, GP, SPI>(a, in, nbr, lnk, ph, mk, sb, ss, ub, acc);
 
     if (EPI == DS_AXPY) {
         T y[24];
