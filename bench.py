@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--block", default="4x4x4x4", help="solve mode: domain shape")
     ap.add_argument("--overlap", type=int, default=0, help="solve mode: overlap s")
     ap.add_argument("--storage", default="f16", choices=["f32", "f16"], help="solve mode: RAS storage")
+    ap.add_argument("--arith", default="fp32", choices=["fp32", "dot2"],
+                    help="solve/sweep modes: arithmetic of the on-chip MR steps (dot2: binary16 operands, FP16 "
+                         "storage)")
     ap.add_argument("--dapply-prec", default="f32", choices=["f64", "f32", "f16"], help="dapply mode: precision")
     ap.add_argument("--n-ras", type=int, default=3)
     ap.add_argument("--n-dominv", type=int, default=5)
@@ -259,7 +262,8 @@ def paper_table(torch, W, ctx, dims, U, eta, kappa=0.126, csw=1.0, tol=1e-14, n_
 def ras_desc(p):
     r = p.ras
     return {"block": list(r.block), "s": r.s, "n_ras": r.n_ras, "n_dominv": r.n_dominv,
-            "storage": {0: "f64", 1: "f32", 2: "f16"}[r.storage], "tol_inner": p.tol_inner}
+            "storage": {0: "f64", 1: "f32", 2: "f16"}[r.storage], "arith": {0: "fp32", 1: "dot2"}[r.arith],
+            "tol_inner": p.tol_inner}
 
 
 def stats_desc(st):
@@ -419,7 +423,7 @@ def domain_kernel_rooflines(torch, W, lat, dims, ras, eta, kappa, csw, stats, n=
     T = {}
     for nr in (1, 2, 6):
         p = W.RasParams.make(block=tuple(ras.block), s=ras.s, n_ras=nr, n_dominv=ras.n_dominv, storage=ras.storage,
-                             kernel=W.BLOCK_FUSED)
+                             kernel=W.BLOCK_FUSED, arith=ras.arith)
         for _ in range(5):
             lat.ras_precondition(p, kappa, csw, r32, v32)
         torch.cuda.synchronize()
@@ -432,7 +436,7 @@ def domain_kernel_rooflines(torch, W, lat, dims, ras, eta, kappa, csw, stats, n=
     sweeps = stats["ras_sweeps"]
     first = sweeps / max(1, ras.n_ras)
     later = sweeps - first
-    st = {1: "f32", 2: "f16"}[ras.storage]
+    st = {1: "f32", 2: "f16"}[ras.storage] + ("_dot2" if ras.arith == W.ARITH_DOT2 else "")
     shape = "x".join(map(str, ras.block))
     key = f"fused_{shape}_s{ras.s}_nd{ras.n_dominv}_{st}"
     res = "res2" if ras.s == 0 else "res1"
@@ -582,11 +586,12 @@ def main():
         lat = W.Lattice(ctx, dims)
         lat.upload_gauge(I.random_gauge(dims, args.eps, 1))
         storage = W.F16 if args.storage == "f16" else W.F32
+        arith = W.ARITH_DOT2 if args.arith == "dot2" else W.ARITH_FP32
         block = tuple(int(v) for v in args.block.split("x"))
         if args.mode == "sweep":
             eta = I.gaussian_source(dims, 2)
             ras = W.RasParams.make(block=block, s=args.overlap, n_ras=args.n_ras, n_dominv=args.n_dominv,
-                                   storage=storage, kernel=W.BLOCK_FUSED)
+                                   storage=storage, kernel=W.BLOCK_FUSED, arith=arith)
             r32 = lat.pack(eta, W.F32)
             v32 = lat.empty(W.F32)
             for _ in range(5):
@@ -603,7 +608,7 @@ def main():
             p = W.SolverParams.make(tol_outer=tol, tol_inner=args.tol_inner, max_outer=200, max_inner=100,
                                     timers=int(args.timers),
                                     ras=W.RasParams.make(block=block, s=args.overlap, n_ras=args.n_ras,
-                                                         n_dominv=args.n_dominv, storage=storage))
+                                                         n_dominv=args.n_dominv, storage=storage, arith=arith))
             if args.even_odd:
                 p = W.SolverParams.make(tol_outer=tol, tol_inner=1e-4, max_outer=200, max_inner=200,
                                         timers=int(args.timers), precond=W.PRECOND_NONE, even_odd=1)

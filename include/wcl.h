@@ -87,6 +87,17 @@ typedef struct wcl_server wcl_server;
                                coloured by the parity of their block coordinates; each sweep solves the
                                colour-0 domains, updates r, then the colour-1 domains, updates r */
 
+/* ---- arithmetic of the on-chip MR domain steps (FP16 storage) ---- */
+#define WCL_ARITH_FP32 0   /* FP32 FMAs on the stored fields (binary16 fields widened inside the FMAs) */
+#define WCL_ARITH_DOT2 1   /* the link and clover products of each MR step take the domain residual
+                              rounded to binary16 (after scaling the domain by a power of two to an RMS
+                              component near 1) and sum in FP32 (two-term dot products), and the
+                              backward-hop terms pass between sites as binary16; projections,
+                              accumulation, the MR scalars and vector updates stay FP32.  FP16 storage,
+                              MR domain solver, RAS, extended domains of at most 256 sites only
+                              (WCL_EINVAL otherwise).  The preconditioner stays homogeneous:
+                              K(2^k r) = 2^k K(r) exactly */
+
 /* RAS parameters (Sec. 2): domains Omega_i are the tiling of the lattice by
  * `block` from the origin; Omega'_i grows each domain by s sites per side in
  * every direction it does not span (overlap depth d = 2s, Sec. 4).
@@ -109,6 +120,7 @@ typedef struct wcl_ras_params {
     int kernel;        /* WCL_BLOCK_* */
     int block_solver;  /* WCL_DOMSOLVE_* */
     int schwarz;       /* WCL_SCHWARZ_* */
+    int arith;         /* WCL_ARITH_* (0 = FP32) */
 } wcl_ras_params;
 
 #define WCL_PRECOND_NONE 0
@@ -281,8 +293,9 @@ int wcl_solve_bicgstab_f64(wcl_lattice* lat, double tol, int max_iter, double ka
  * depth, N_dominv, NRAS; Sec. 5 scans them by hand) plus the domain shape,
  * storage precision, inner tolerance and the D-apply's lanes per site, by
  * timing complete nested solves of eta on this lattice: stage 1 scans
- * domain shape {4^4, 4^3x8, 8^4} x overlap {0, 1} x storage (bit 0 of
- * storage_mask: FP32, bit 1: FP16; 0 = both); stage 2 scans N_dominv
+ * domain shape {4^4, 4^3x8, 8^4} x overlap {0, 1} x storage and arithmetic
+ * (bit 0 of storage_mask: FP32; bit 1: FP16; bit 2: FP16 with
+ * WCL_ARITH_DOT2 where the fused solver runs; 0 = all); stage 2 scans N_dominv
  * 2..8 x NRAS 1..8; stage 3 the inner tolerance {1e-2, ..., 1e-6} and lanes
  * per site {1, 2}; stage 4 N_dominv and NRAS one step around the best at the
  * chosen tolerance.  Candidates that do not converge within 10 outer

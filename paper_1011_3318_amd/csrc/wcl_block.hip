@@ -761,6 +761,10 @@ struct SiteFields {
     }
     // q = A r = r + ck C r
     WCL_DEV void site_term(const float r[24], float ck, float q[24]) const { clover_term(c, r, ck, q); }
+    // the forms used inside the MR steps (the same arithmetic here)
+    template <int MU, bool DAG>
+    WCL_DEV void step_apply(const float h[12], float w[12]) const { apply<MU, DAG>(h, w); }
+    WCL_DEV void step_site_term(const float r[24], float ck, float q[24]) const { site_term(r, ck, q); }
 };
 
 // FP16 storage: rows 0,1 of the links and the clover stay in registers as the
@@ -894,6 +898,219 @@ struct SiteFields<WCL_F16> {
             for (int j = 0; j < 12; ++j) q[12 * bk + j] = fmad(f, y[j], x[j]);
         }
     }
+    template <int MU, bool DAG>
+    WCL_DEV void step_apply(const float h[12], float w[12]) const { apply<MU, DAG>(h, w); }
+    WCL_DEV void step_site_term(const float r[24], float ck, float q[24]) const { site_term(r, ck, q); }
+};
+
+// Complex products on packed binary16 pairs a = (ar, ai), b = (br, bi) with
+// b' = (bi, br), as two-term dot products with an FP32 sum (v_dot2_f32_f16:
+// both binary16 products are exact in FP32):
+//   Re(a b) = dot2n(a, b),  Im(a b) = dot2(a, b'),
+//   Re(conj(a) b) = dot2(a, b),  Im(conj(a) b) = dot2n(a, b').
+// dot2n negates the second product through the instruction's neg_hi
+// operand modifier (the compiler does not form it from the source).
+WCL_DEV float dot2(h2v a, h2v b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
+WCL_DEV float dot2n(h2v a, h2v b, float c) {
+    float d;
+    asm("v_dot2_f32_f16 %0, %1, %2, %3 neg_hi:[0,1,0]" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+WCL_DEV h2v pack2(float x, float y) { return h2v{(_Float16)x, (_Float16)y}; }
+
+// FP16 storage with binary16 operands inside the MR steps: the fields as in
+// SiteFields<WCL_F16> (row 2 of each link rebuilt in FP32 at load and
+// rounded to binary16 as well), and each step's products of the links and
+// the clover with rho take rho rounded to binary16 (pairs (re, im) and
+// (im, re)) as v_dot2 operands, summed in FP32, and each site publishes its
+// backward-hop terms U^dag P+ rho as binary16 pairs (48 instead of 72 LDS
+// words per site).  Projections, accumulation and the MR vector work stay
+// FP32.  The kernel scales each domain's rho by a
+// power of two to an RMS component near 1 before the steps (MR commutes with
+// the scaling), so the binary16 operands neither overflow nor lose precision
+// to small magnitudes.  The residual updates between sweeps use the
+// mixed-precision FMA forms (FP32 operands, unscaled).
+struct SiteFieldsDot {
+    h2v u[4][9];   // U_mu(x), element (row, col) at 3 row + col, binary16
+    h2v c[36];     // clover blocks, binary16 of value / scale
+    float cs;
+    float zr;      // an opaque zero: see SiteFields<WCL_F16>
+    WCL_DEV void zero() {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) u[mu][k] = h2v{(_Float16)0.f, (_Float16)0.f};
+#pragma unroll
+        for (int k = 0; k < 36; ++k) c[k] = h2v{(_Float16)0.f, (_Float16)0.f};
+        cs = 0.f;
+        zr = 0.f;
+        asm volatile("" : "+v"(zr));
+    }
+    WCL_DEV void refresh() {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) asm volatile("" : "+v"(u[mu][k]));
+#pragma unroll
+        for (int k = 0; k < 36; ++k) asm volatile("" : "+v"(c[k]));
+    }
+    template <int MU>
+    WCL_DEV float uk(int k) const { return (float)((k & 1) ? u[MU][k >> 1].y : u[MU][k >> 1].x); }
+    WCL_DEV float ck_(int k) const { return (float)((k & 1) ? c[k >> 1].y : c[k >> 1].x); }
+    WCL_DEV void load(const BlockArgs& a, int gi) {
+        const h4v* gp = (const h4v*)a.gauge;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            float t[18];
+#pragma unroll
+            for (int g = 0; g < 3; ++g) {
+                const h4v v = gp[tix(3 * mu + g, gi, 12)];
+                u[mu][2 * g] = h2v{v.x, v.y};
+                u[mu][2 * g + 1] = h2v{v.z, v.w};
+                t[4 * g] = (float)v.x;
+                t[4 * g + 1] = (float)v.y;
+                t[4 * g + 2] = (float)v.z;
+                t[4 * g + 3] = (float)v.w;
+            }
+            reconstruct_row2(t);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) u[mu][6 + k] = pack2(t[12 + 2 * k], t[12 + 2 * k + 1]);
+        }
+        const h8v* cp = (const h8v*)a.clover;
+#pragma unroll
+        for (int g = 0; g < 9; ++g) {
+            const h8v v = cp[tix(g, gi, 9)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) c[4 * g + j] = h2v{v[2 * j], v[2 * j + 1]};
+        }
+        cs = ((const float*)((const char*)a.clover + half_clover_scale_offset(a.g.V)))[gi];
+    }
+    // w = U_mu(x) h or U_mu(x)^dag h, FP32 operands (mixed-precision FMAs)
+    template <int MU, bool DAG>
+    WCL_DEV void apply(const float h[12], float w[12]) const {
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                float re = zr, im = zr;
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const int e = DAG ? 3 * b + a : 3 * a + b;
+                    const float ur = uk<MU>(2 * e), uv = uk<MU>(2 * e + 1);
+                    const float ui = DAG ? -uv : uv;
+                    const float hr = h[6 * sp + 2 * b], hi = h[6 * sp + 2 * b + 1];
+                    re = fmad(ur, hr, re);
+                    re = fmad(-ui, hi, re);
+                    im = fmad(ur, hi, im);
+                    im = fmad(ui, hr, im);
+                }
+                w[6 * sp + 2 * a] = re;
+                w[6 * sp + 2 * a + 1] = im;
+            }
+    }
+    // q = r + ck C r, FP32 operands
+    WCL_DEV void site_term(const float r[24], float ck, float q[24]) const {
+        const float f = ck * cs;
+#pragma unroll
+        for (int bk = 0; bk < 2; ++bk) {
+            const int o = 36 * bk;
+            const float* x = r + 12 * bk;
+            float y[12];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                y[2 * a] = fmad(ck_(o + a), x[2 * a], zr);
+                y[2 * a + 1] = fmad(ck_(o + a), x[2 * a + 1], zr);
+            }
+            int k = 0;
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+#pragma unroll
+                for (int b = a + 1; b < 6; ++b, ++k) {
+                    const float re = ck_(o + 6 + 2 * k), im = ck_(o + 6 + 2 * k + 1);
+                    y[2 * a] = fmad(re, x[2 * b], y[2 * a]);
+                    y[2 * a] = fmad(-im, x[2 * b + 1], y[2 * a]);
+                    y[2 * a + 1] = fmad(re, x[2 * b + 1], y[2 * a + 1]);
+                    y[2 * a + 1] = fmad(im, x[2 * b], y[2 * a + 1]);
+                    y[2 * b] = fmad(re, x[2 * a], y[2 * b]);
+                    y[2 * b] = fmad(im, x[2 * a + 1], y[2 * b]);
+                    y[2 * b + 1] = fmad(re, x[2 * a + 1], y[2 * b + 1]);
+                    y[2 * b + 1] = fmad(-im, x[2 * a], y[2 * b + 1]);
+                }
+#pragma unroll
+            for (int j = 0; j < 12; ++j) q[12 * bk + j] = fmad(f, y[j], x[j]);
+        }
+    }
+    // the same products with h rounded to binary16 (v_dot2)
+    template <int MU, bool DAG>
+    WCL_DEV void step_apply(const float h[12], float w[12]) const {
+        h2v hp[6], hs[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            hp[k] = pack2(h[2 * k], h[2 * k + 1]);
+            hs[k] = pack2(h[2 * k + 1], h[2 * k]);
+        }
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                float re = zr, im = zr;
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const h2v U = u[MU][DAG ? 3 * b + a : 3 * a + b];
+                    if (DAG) {
+                        re = dot2(U, hp[3 * sp + b], re);
+                        im = dot2n(U, hs[3 * sp + b], im);
+                    } else {
+                        re = dot2n(U, hp[3 * sp + b], re);
+                        im = dot2(U, hs[3 * sp + b], im);
+                    }
+                }
+                w[6 * sp + 2 * a] = re;
+                w[6 * sp + 2 * a + 1] = im;
+            }
+    }
+    WCL_DEV void step_site_term(const float r[24], float ck, float q[24]) const {
+        const float f = ck * cs;
+#pragma unroll
+        for (int bk = 0; bk < 2; ++bk) {
+            const int o = 36 * bk;
+            const float* x = r + 12 * bk;
+            h2v xp[6], xs[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                xp[k] = pack2(x[2 * k], x[2 * k + 1]);
+                xs[k] = pack2(x[2 * k + 1], x[2 * k]);
+            }
+            float y[12];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                y[2 * a] = fmad(ck_(o + a), x[2 * a], zr);
+                y[2 * a + 1] = fmad(ck_(o + a), x[2 * a + 1], zr);
+            }
+            int k = 0;
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+#pragma unroll
+                for (int b = a + 1; b < 6; ++b, ++k) {
+                    const h2v C = c[o / 2 + 3 + k];   // C_ab; C_ba = conj(C_ab)
+                    y[2 * a] = dot2n(C, xp[b], y[2 * a]);
+                    y[2 * a + 1] = dot2(C, xs[b], y[2 * a + 1]);
+                    y[2 * b] = dot2(C, xp[a], y[2 * b]);
+                    y[2 * b + 1] = dot2n(C, xs[a], y[2 * b + 1]);
+                }
+#pragma unroll
+            for (int j = 0; j < 12; ++j) q[12 * bk + j] = fmad(f, y[j], x[j]);
+        }
+    }
+};
+
+template <int GP, bool DOT>
+struct FusedFields {
+    using type = SiteFields<GP>;
+};
+template <>
+struct FusedFields<WCL_F16, true> {
+    using type = SiteFieldsDot;
 };
 
 #ifndef WCL_FUSED_MINWAVES
@@ -902,11 +1119,22 @@ struct SiteFields<WCL_F16> {
 // RES: 0 = no residual update (first sweep); 1 = r_j = src - D vprev from
 // all eight hops; 2 = r_j = src - (the hops of D vprev that leave the
 // domain), src being the previous sweep's final MR residual (no overlap).
-template <int GP, int SRC, int VP, int NT, int RES>
-__global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs a, int write_vj) {
+// DOT: the published backward terms are binary16 pairs (48 instead of 72
+// LDS words per site).  Three domains per CU would then fit the LDS but not
+// the registers: forced to 168 VGPRs the kernel spills and runs slower
+// (measured 850 against 770 us per 32^4 RAS application), so it keeps two.
+template <bool DOT>
+struct FusedShape {
+    static constexpr int lds_words = DOT ? 48 : 72;
+    static constexpr int min_waves = WCL_FUSED_MINWAVES;
+};
+
+template <int GP, int SRC, int VP, int NT, int RES, bool DOT>
+__global__ __launch_bounds__(NT, FusedShape<DOT>::min_waves) void k_blk_fused(BlockArgs a, int write_vj) {
     extern __shared__ float lds[];
     float* s_rho = lds;                 // [24][NT]
-    float* s_bwd = lds + 24 * NT;       // [4][12][NT]
+    float* s_bwd = lds + 24 * NT;       // [4][12][NT] FP32, or [4][6][NT] binary16 pairs (DOT)
+    h2v* s_bwd16 = (h2v*)s_bwd;
     __shared__ double s_red[3 * (NT / 64)];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int rhs = lb % a.nrhs, blk = lb / a.nrhs;
@@ -917,7 +1145,7 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
     int nf[4], nb[4];
     float phf[4], phb[4];
     float rho[24], xs[24];
-    SiteFields<GP> F;
+    typename FusedFields<GP, DOT>::type F;
     F.zero();
 #pragma unroll
     for (int k = 0; k < 24; ++k) {
@@ -1022,6 +1250,29 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
                 SpinorIO<VP>::store((char*)a.rout + rhs * a.rout_stride, a.g.V, gi, rho);
         }
     }
+    // binary16 operands: scale the domain's rho by 2^-e, 2^e near its RMS
+    // component (exact in FP32; the solution and the final residual are
+    // scaled back at the end)
+    float scale = 1.f;
+    if constexpr (DOT) {
+        double d[3] = {0.0, 0.0, 0.0};
+        if (active) {
+            float f = 0.f;
+#pragma unroll
+            for (int k = 0; k < 24; ++k) f = fmad(rho[k], rho[k], f);
+            d[0] = f;
+        }
+        wg_allreduce3<NT / 64>(d, s_red);
+        const double ms = d[0] / (24.0 * a.B.ev);
+        if (ms > 0.0 && ms < 1e300) {
+            int e = 0;
+            frexp(sqrt(ms), &e);
+            scale = ldexpf(1.f, e);
+            const float inv = ldexpf(1.f, -e);
+#pragma unroll
+            for (int k = 0; k < 24; ++k) rho[k] *= inv;
+        }
+    }
     // rho lives in LDS between steps: only its owner thread writes it
 #pragma unroll
     for (int k = 0; k < 24; ++k) s_rho[k * NT + l] = rho[k];
@@ -1032,10 +1283,14 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
             float r[24], h[12], w[12];
 #pragma unroll
             for (int k = 0; k < 24; ++k) r[k] = s_rho[k * NT + l];
-#define WCL_BWD(MU)                                                         \
-    spin_project<MU, false>(r, h);                                          \
-    F.template apply<MU, true>(h, w);                                       \
-    _Pragma("unroll") for (int k = 0; k < 12; ++k) s_bwd[(MU * 12 + k) * NT + l] = w[k];
+#define WCL_BWD(MU)                                                                           \
+    spin_project<MU, false>(r, h);                                                            \
+    F.template step_apply<MU, true>(h, w);                                                    \
+    if constexpr (DOT) {                                                                      \
+        _Pragma("unroll") for (int k = 0; k < 6; ++k) s_bwd16[(MU * 6 + k) * NT + l] = pack2(w[2 * k], w[2 * k + 1]); \
+    } else {                                                                                  \
+        _Pragma("unroll") for (int k = 0; k < 12; ++k) s_bwd[(MU * 12 + k) * NT + l] = w[k]; \
+    }
             WCL_BWD(0) WCL_BWD(1) WCL_BWD(2) WCL_BWD(3)
 #undef WCL_BWD
         }
@@ -1046,7 +1301,7 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
             float r[24];
 #pragma unroll
             for (int k = 0; k < 24; ++k) r[k] = s_rho[k * NT + l];
-            F.site_term(r, ck, q);
+            F.step_site_term(r, ck, q);
         }
         {
             float s[24], h[12], w[12];
@@ -1054,11 +1309,19 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
     if (nf[MU] >= 0) {                                                                          \
         _Pragma("unroll") for (int k = 0; k < 24; ++k) s[k] = s_rho[k * NT + nf[MU]];         \
         spin_project<MU, true>(s, h);                                                           \
-        F.template apply<MU, false>(h, w);                                                      \
+        F.template step_apply<MU, false>(h, w);                                                 \
         spin_accumulate<MU, true>(w, mk * phf[MU], q);                                          \
     }                                                                                           \
     if (nb[MU] >= 0) {                                                                          \
-        _Pragma("unroll") for (int k = 0; k < 12; ++k) w[k] = s_bwd[(MU * 12 + k) * NT + nb[MU]]; \
+        if constexpr (DOT) {                                                                    \
+            _Pragma("unroll") for (int k = 0; k < 6; ++k) {                                     \
+                const h2v t = s_bwd16[(MU * 6 + k) * NT + nb[MU]];                              \
+                w[2 * k] = (float)t.x;                                                          \
+                w[2 * k + 1] = (float)t.y;                                                      \
+            }                                                                                   \
+        } else {                                                                                \
+            _Pragma("unroll") for (int k = 0; k < 12; ++k) w[k] = s_bwd[(MU * 12 + k) * NT + nb[MU]]; \
+        }                                                                                       \
         spin_accumulate<MU, false>(w, mk * phb[MU], q);                                         \
     }
             WCL_HOPS(0) WCL_HOPS(1) WCL_HOPS(2) WCL_HOPS(3)
@@ -1117,9 +1380,13 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
             // this sweep's final MR residual, the next sweep's starting point
             float rn[24];
 #pragma unroll
-            for (int k = 0; k < 24; ++k) rn[k] = s_rho[k * NT + l];
+            for (int k = 0; k < 24; ++k) rn[k] = s_rho[k * NT + l] * scale;
             SpinorIO<VP>::store((char*)a.rout + rhs * a.rout_stride, a.g.V, gi, rn);
         }
+    }
+    if constexpr (DOT) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) xs[k] *= scale;
     }
     char* out = (char*)a.out + rhs * a.out_stride;
     if (a.accumulate) {
@@ -1136,14 +1403,14 @@ __global__ __launch_bounds__(NT, WCL_FUSED_MINWAVES) void k_blk_fused(BlockArgs 
 
 int fused_threads(int ev) { return ev <= 256 ? 256 : 0; }
 
-template <int GP, int SRC, int VP, int NT, int RES>
+template <int GP, int SRC, int VP, int NT, int RES, bool DOT>
 static int launch_fused_t(const BlockArgs& a, hipStream_t st) {
-    const size_t lds = (size_t)72 * NT * sizeof(float);
+    const size_t lds = (size_t)FusedShape<DOT>::lds_words * NT * sizeof(float);
     // dynamic LDS above the 64 KB default; set once per instantiation (thread-safe static)
-    static const hipError_t attr = hipFuncSetAttribute((const void*)k_blk_fused<GP, SRC, VP, NT, RES>,
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_blk_fused<GP, SRC, VP, NT, RES, DOT>,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     WCL_HIP(attr);
-    k_blk_fused<GP, SRC, VP, NT, RES><<<a.B.nblocks * a.nrhs, NT, lds, st>>>(a, a.vj != nullptr);
+    k_blk_fused<GP, SRC, VP, NT, RES, DOT><<<a.B.nblocks * a.nrhs, NT, lds, st>>>(a, a.vj != nullptr);
     WCL_HIP(hipGetLastError());
     return WCL_OK;
 }
@@ -1151,16 +1418,18 @@ static int launch_fused_t(const BlockArgs& a, hipStream_t st) {
 int launch_blk_fused(const BlockArgs& a, int gp, int src_prec, hipStream_t st) {
     const int nt = fused_threads(a.B.ev);
     const int res = a.vprev == nullptr ? 0 : (a.res_boundary ? 2 : 1);
-#define WCL_F(G, S, NT)                                                                    \
-    if (gp == G && src_prec == S && nt == NT)                                              \
-        return res == 0   ? launch_fused_t<G, S, G, NT, 0>(a, st)                          \
-               : res == 1 ? launch_fused_t<G, S, G, NT, 1>(a, st)                          \
-                          : launch_fused_t<G, S, G, NT, 2>(a, st)
-    WCL_F(WCL_F32, WCL_F32, 256);
-    WCL_F(WCL_F16, WCL_F32, 256);
-    WCL_F(WCL_F16, WCL_F16, 256);
+#define WCL_F(G, S, NT, D)                                                                 \
+    if (gp == G && src_prec == S && nt == NT && (a.dot2 != 0) == D)                        \
+        return res == 0   ? launch_fused_t<G, S, G, NT, 0, D>(a, st)                       \
+               : res == 1 ? launch_fused_t<G, S, G, NT, 1, D>(a, st)                       \
+                          : launch_fused_t<G, S, G, NT, 2, D>(a, st)
+    WCL_F(WCL_F32, WCL_F32, 256, false);
+    WCL_F(WCL_F16, WCL_F32, 256, false);
+    WCL_F(WCL_F16, WCL_F16, 256, false);
+    WCL_F(WCL_F16, WCL_F32, 256, true);
+    WCL_F(WCL_F16, WCL_F16, 256, true);
 #undef WCL_F
-    wcl_set_error("fused domain solver: unsupported case (storage %d, source %d, extended volume %d)", gp, src_prec,
-                  a.B.ev);
+    wcl_set_error("fused domain solver: unsupported case (storage %d, source %d, extended volume %d, dot2 %d)", gp,
+                  src_prec, a.B.ev, a.dot2);
     return WCL_EINVAL;
 }

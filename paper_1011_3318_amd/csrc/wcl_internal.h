@@ -104,6 +104,7 @@ struct Blocks {
     int n_ras, n_dominv;
     int solver;    // WCL_DOMSOLVE_*
     int schwarz;   // WCL_SCHWARZ_*
+    int arith;     // WCL_ARITH_*
 };
 
 // ------------------------------------------------------ storage -------

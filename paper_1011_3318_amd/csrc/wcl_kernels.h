@@ -143,6 +143,7 @@ struct BlockArgs {
     double* bpart[3];    // truncated BiCGStab partial sums: <rhat, r>, <rhat, v>, (<t, s>, |t|^2)
     double* dsc;         // truncated BiCGStab per-(rhs, domain) scalars [rhs][nblocks][8]:
                          // rho, alpha, omega, rho_old (complex)
+    int dot2;            // on-chip MR steps with binary16 operands and FP32 sums (FP16 storage only)
 };
 
 int launch_blk_project(const BlockArgs& a, int src_prec, int bicgstab, hipStream_t st);

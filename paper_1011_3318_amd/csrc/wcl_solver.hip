@@ -227,6 +227,16 @@ int make_blocks(const wcl_lattice* lat, const wcl_ras_params* p, Blocks* B) {
     B->n_dominv = p->n_dominv;
     B->solver = p->block_solver;
     B->schwarz = p->schwarz;
+    B->arith = p->arith;
+    if (p->arith != WCL_ARITH_FP32 && p->arith != WCL_ARITH_DOT2) {
+        wcl_set_error("RAS arithmetic %d unknown", p->arith);
+        return WCL_EINVAL;
+    }
+    if (p->arith == WCL_ARITH_DOT2 &&
+        (p->storage != WCL_F16 || p->block_solver != WCL_DOMSOLVE_MR || p->schwarz != WCL_SCHWARZ_RAS)) {
+        wcl_set_error("binary16-operand MR steps need FP16 storage, the MR domain solver and RAS");
+        return WCL_EINVAL;
+    }
     // the additive sum gathers each site from its own domain and the two
     // neighbouring ones in every direction, which covers every extended
     // domain holding it when s <= b
@@ -264,6 +274,11 @@ static int pick_kernel(const Blocks& B, int requested, bool* fused) {
         return WCL_EINVAL;
     }
     *fused = requested != WCL_BLOCK_SPLIT && fits && !variant;
+    if (B.arith == WCL_ARITH_DOT2 && !*fused) {
+        wcl_set_error("binary16-operand MR steps run in the fused domain solver only (extended domains of at most "
+                      "256 sites, kernel not forced to the split path)");
+        return WCL_EINVAL;
+    }
     return WCL_OK;
 }
 
@@ -425,6 +440,7 @@ static int ras_run(wcl_lattice* lat, const Blocks& B, bool fused, int storage, d
     BlockArgs a{};
     a.g = lat->g;
     a.B = B;
+    a.dot2 = B.arith == WCL_ARITH_DOT2;
     a.gauge = lat->gauge[storage];
     a.clover = lat->clover[storage];
     a.NE = NE;

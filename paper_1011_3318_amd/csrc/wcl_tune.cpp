@@ -33,7 +33,7 @@ std::string tune_key(const wcl_lattice* lat, int nrhs, double kappa, double csw,
 
 // One line per entry:
 // {"key": "...", "block": [b0,b1,b2,b3], "s": s, "n_ras": n, "n_dominv": n, "storage": p,
-//  "tol_inner": t, "lps": l, "ms": m}
+//  "arith": a, "tol_inner": t, "lps": l, "ms": m}
 bool cache_lookup(const char* path, const std::string& key, Cand* c, double* ms) {
     FILE* f = fopen(path, "r");
     if (!f) return false;
@@ -42,17 +42,18 @@ bool cache_lookup(const char* path, const std::string& key, Cand* c, double* ms)
     const std::string pat = "\"key\": \"" + key + "\"";
     while (fgets(line, sizeof line, f)) {
         if (!strstr(line, pat.c_str())) continue;
-        int b[4], s, nr, nd, st, lps;
+        int b[4], s, nr, nd, st, ar, lps;
         double tol, m;
         const char* q = strstr(line, "\"block\"");
         if (q && sscanf(q, "\"block\": [%d, %d, %d, %d], \"s\": %d, \"n_ras\": %d, \"n_dominv\": %d, \"storage\": %d, "
-                           "\"tol_inner\": %lf, \"lps\": %d, \"ms\": %lf",
-                        &b[0], &b[1], &b[2], &b[3], &s, &nr, &nd, &st, &tol, &lps, &m) == 11) {
+                           "\"arith\": %d, \"tol_inner\": %lf, \"lps\": %d, \"ms\": %lf",
+                        &b[0], &b[1], &b[2], &b[3], &s, &nr, &nd, &st, &ar, &tol, &lps, &m) == 12) {
             for (int mu = 0; mu < 4; ++mu) c->p.ras.block[mu] = b[mu];
             c->p.ras.s = s;
             c->p.ras.n_ras = nr;
             c->p.ras.n_dominv = nd;
             c->p.ras.storage = st;
+            c->p.ras.arith = ar;
             c->p.ras.kernel = WCL_BLOCK_AUTO;
             c->p.tol_inner = tol;
             c->p.precond = WCL_PRECOND_RAS;
@@ -70,9 +71,9 @@ void cache_store(const char* path, const std::string& key, const Cand& c, double
     if (!f) return;
     fprintf(f,
             "{\"key\": \"%s\", \"block\": [%d, %d, %d, %d], \"s\": %d, \"n_ras\": %d, \"n_dominv\": %d, "
-            "\"storage\": %d, \"tol_inner\": %.3e, \"lps\": %d, \"ms\": %.4f}\n",
+            "\"storage\": %d, \"arith\": %d, \"tol_inner\": %.3e, \"lps\": %d, \"ms\": %.4f}\n",
             key.c_str(), c.p.ras.block[0], c.p.ras.block[1], c.p.ras.block[2], c.p.ras.block[3], c.p.ras.s,
-            c.p.ras.n_ras, c.p.ras.n_dominv, c.p.ras.storage, c.p.tol_inner, c.lps, ms);
+            c.p.ras.n_ras, c.p.ras.n_dominv, c.p.ras.storage, c.p.ras.arith, c.p.tol_inner, c.lps, ms);
     fclose(f);
 }
 
@@ -81,11 +82,11 @@ void cache_store(const char* path, const std::string& key, const Cand& c, double
 extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, double kappa, double csw,
                             const void* eta_dev, int nrhs, int storage_mask, const char* cache_path,
                             wcl_solver_params* best, double* best_ms, void* stream) {
-    if (!lat || !base || !eta_dev || nrhs < 1 || !best || storage_mask < 0 || storage_mask > 3) {
+    if (!lat || !base || !eta_dev || nrhs < 1 || !best || storage_mask < 0 || storage_mask > 7) {
         wcl_set_error("wcl_autotune: bad argument");
         return WCL_EINVAL;
     }
-    if (storage_mask == 0) storage_mask = 3;
+    if (storage_mask == 0) storage_mask = 7;
     WCL_HIP(hipSetDevice(lat->ctx->device));
     hipStream_t st = (hipStream_t)stream;
     const std::string key = tune_key(lat, nrhs, kappa, csw, storage_mask);
@@ -150,16 +151,19 @@ extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, dou
             bestc = c;
         }
     };
-    // stage 1: domain shape x overlap x storage
+    // stage 1: domain shape x overlap x storage and arithmetic (storage_mask
+    // bit 0: FP32, bit 1: FP16, bit 2: FP16 with binary16-operand MR steps;
+    // a combination the fused solver cannot run fails validation and drops out)
     const int shapes[3][4] = {{4, 4, 4, 4}, {4, 4, 4, 8}, {8, 8, 8, 8}};
     for (const auto& sh : shapes)
         for (int s = 0; s <= 1; ++s)
-            for (int storage : {WCL_F32, WCL_F16}) {
-                if (!(storage_mask & (storage == WCL_F32 ? 1 : 2))) continue;
+            for (int v = 0; v < 3; ++v) {
+                if (!(storage_mask & (1 << v))) continue;
                 Cand c = cur;
                 for (int mu = 0; mu < 4; ++mu) c.p.ras.block[mu] = sh[mu];
                 c.p.ras.s = s;
-                c.p.ras.storage = storage;
+                c.p.ras.storage = v == 0 ? WCL_F32 : WCL_F16;
+                c.p.ras.arith = v == 2 ? WCL_ARITH_DOT2 : WCL_ARITH_FP32;
                 c.p.ras.n_dominv = 4;
                 c.p.ras.n_ras = 3;
                 c.p.ras.kernel = WCL_BLOCK_AUTO;

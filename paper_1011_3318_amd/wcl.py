@@ -20,6 +20,7 @@ F64, F32, F16 = 0, 1, 2
 BLOCK_AUTO, BLOCK_FUSED, BLOCK_SPLIT = 0, 1, 2
 DOMSOLVE_MR, DOMSOLVE_JACOBI, DOMSOLVE_BICGSTAB = 0, 1, 2
 SCHWARZ_RAS, SCHWARZ_AS, SCHWARZ_SAP = 0, 1, 2
+ARITH_FP32, ARITH_DOT2 = 0, 1
 PRECOND_NONE, PRECOND_RAS = 0, 1
 OK, EINVAL, ENOMEM, EUNITARITY, ENOTCONV, EBREAKDOWN, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 PENDING = 1
@@ -35,12 +36,13 @@ class WclError(RuntimeError):
 
 class RasParams(C.Structure):
     _fields_ = [("block", C.c_int * 4), ("s", C.c_int), ("n_ras", C.c_int), ("n_dominv", C.c_int),
-                ("storage", C.c_int), ("kernel", C.c_int), ("block_solver", C.c_int), ("schwarz", C.c_int)]
+                ("storage", C.c_int), ("kernel", C.c_int), ("block_solver", C.c_int), ("schwarz", C.c_int),
+                ("arith", C.c_int)]
 
     @classmethod
     def make(cls, block=(4, 4, 4, 4), s=0, n_ras=3, n_dominv=4, storage=F32, kernel=BLOCK_AUTO,
-             block_solver=DOMSOLVE_MR, schwarz=SCHWARZ_RAS):
-        return cls((C.c_int * 4)(*block), s, n_ras, n_dominv, storage, kernel, block_solver, schwarz)
+             block_solver=DOMSOLVE_MR, schwarz=SCHWARZ_RAS, arith=ARITH_FP32):
+        return cls((C.c_int * 4)(*block), s, n_ras, n_dominv, storage, kernel, block_solver, schwarz, arith)
 
 
 class SolverParams(C.Structure):
@@ -352,12 +354,18 @@ lib.wcl_autotune.argtypes = [C.c_void_p, C.POINTER(SolverParams), C.c_double, C.
 
 
 def autotune(lat: Lattice, base: SolverParams, kappa: float, csw: float, eta: torch.Tensor, nrhs: int = 1,
-             cache_path: str | None = None, stream=None, storage=None):
+             cache_path: str | None = None, stream=None, storage=None, storage_mask=None):
     """Autotuned solver parameters for this lattice, timed on the tuning source
-    eta (see include/wcl.h).  storage: None = FP32 and FP16, or F32 / F16 only."""
+    eta (see include/wcl.h).  storage: None = every candidate, F32 = FP32
+    storage only, F16 = FP16 storage with either arithmetic; storage_mask
+    (bit 0 FP32, bit 1 FP16, bit 2 FP16 with binary16-operand MR steps)
+    overrides it."""
     best = SolverParams()
     ms = C.c_double()
-    mask = 0 if storage is None else (1 if storage == F32 else 2)
+    if storage_mask is not None:
+        mask = storage_mask
+    else:
+        mask = 0 if storage is None else (1 if storage == F32 else 6)
     check(lib.wcl_autotune(lat.h, C.byref(base), kappa, csw, _ptr(eta), nrhs, mask,
                            cache_path.encode() if cache_path else None, C.byref(best), C.byref(ms), _stream(stream)))
     return best, ms.value
