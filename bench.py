@@ -871,8 +871,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64/f32/f16 (outer BiCGStab FP64; inner BiCGStab FP32; RAS domain solves in FP32 arithmetic "
-                 "on FP16 storage of links, clover and sweep fields)",
+        "dtype": "f64/f32/f16 (outer BiCGStab FP64; inner BiCGStab FP32; RAS domain solves on FP16 storage of "
+                 "links, clover and sweep fields, " +
+                 ("MR steps with binary16 operands and FP32 sums (v_dot2_f32_f16), FP32 vector work"
+                  if tuned.ras.arith == W.ARITH_DOT2 else "FP32 arithmetic") + ")",
         "data": "synthetic (seeded random SU(3) gauge field eps=0.3 and Gaussian source)",
         "config": {"workload": "32^4 nested RAS-BiCGStab solve to 1e-10 (eps 0.3, kappa 0.125, c_sw 1.0; "
                                "FP16-storage domain solves, domain shape autotuned over 4^4, 4^3x8, 8^4)",

@@ -121,9 +121,15 @@ extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, dou
     }
     Cand bestc = cur;
     double bms = 1e30;
-    // time = best of two complete solves (the first also warms the workspace);
-    // a candidate that needs more than 10 outer iterations is no contender and
-    // is dropped, as is the second solve of one more than 3 x slower than the best
+    // time = best of two complete solves (the first also warms the workspace),
+    // scaled to the tolerance: t x log(tol) / log(achieved true residual).  A
+    // solve that ends well below the tolerance has bought extra reduction with
+    // its last iteration; ranking by the estimated time to reach the tolerance
+    // itself removes that step of one iteration more or less, which depends on
+    // the source, so the choice carries over to other sources.  A candidate that
+    // needs more than 10 outer iterations is no contender and is dropped, as is
+    // the second solve of one more than 3 x slower than the best
+    const double ltol = std::log(std::min(std::max(base->tol_outer, 1e-300), 0.5));
     auto measure = [&](const Cand& c0, double* ms) -> bool {
         Blocks B;
         if (make_blocks(lat, &c0.p.ras, &B) != WCL_OK) return false;
@@ -137,7 +143,11 @@ extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, dou
             wcl_solve_stats s{};
             int r = nested_solve(lat, ws, &c.p, kappa, csw, eta_dev, phi, nrhs, &s, st);
             if (r != WCL_OK || !s.converged) ok = false;
-            else t = std::min(t, s.ms_total);
+            else {
+                const double lres = std::log(std::max(s.true_resid, 1e-300));
+                const double f = lres < ltol ? ltol / lres : 1.0;
+                t = std::min(t, s.ms_total * f);
+            }
             if (ok && t > 3.0 * bms) break;
         }
         lat->lps = saved;
