@@ -299,20 +299,23 @@ int wcl_solve_bicgstab_f64(wcl_lattice* lat, double tol, int max_iter, double ka
  * 2..8 x NRAS 1..8; stage 3 the inner tolerance {1e-2, ..., 1e-6} and lanes
  * per site {1, 2}; stage 4 N_dominv and NRAS one step around the best at the
  * chosen tolerance.  Candidates that do not converge within 10 outer
- * iterations are skipped; the others are ranked by their solve time scaled
- * to the tolerance, t x log(tol_outer) / log(achieved true residual), which
- * credits a solve that ends below the tolerance for its extra reduction
- * (the step of one iteration more or less depends on the source).  eta is
- * a tuning source: the chosen parameters serve any source on this lattice.
+ * iterations are skipped; the others are ranked by the sum over the nsrc
+ * tuning sources of their solve times, each credited for ending below the
+ * tolerance by the share of an iteration that geometric convergence would
+ * have saved (f = log(tol_outer) / log(achieved true residual), credit
+ * min(n (1 - f), 1/2) of n inner iterations): the step of one iteration more
+ * or less depends on the source.  eta_dev holds nsrc tuning sources of nrhs
+ * right-hand sides each, one after the other (1 <= nsrc <= 16); the chosen
+ * parameters serve any source on this lattice.
  * With cache_path != NULL the result is read from / appended to that
  * JSON-lines file, keyed by device architecture, dims, nrhs, kappa, c_sw and
  * storage_mask.  *best receives the chosen parameters (tol_outer, max_* and
  * max_restarts are copied from *base; MR domain solves inside RAS, full D),
- * *best_ms its scaled solve time; the lattice keeps the chosen lanes per
+ * *best_ms its ranking time; the lattice keeps the chosen lanes per
  * site.  Blocks until done. */
 int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, double kappa, double csw, const void* eta_dev,
-                 int nrhs, int storage_mask, const char* cache_path, wcl_solver_params* best, double* best_ms,
-                 void* stream);
+                 int nrhs, int nsrc, int storage_mask, const char* cache_path, wcl_solver_params* best,
+                 double* best_ms, void* stream);
 
 /* ---- serving (continuous batching of solve requests) ----
  * A server owns resident gauge/clover fields per registered configuration and

@@ -80,9 +80,10 @@ void cache_store(const char* path, const std::string& key, const Cand& c, double
 }  // namespace
 
 extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, double kappa, double csw,
-                            const void* eta_dev, int nrhs, int storage_mask, const char* cache_path,
+                            const void* eta_dev, int nrhs, int nsrc, int storage_mask, const char* cache_path,
                             wcl_solver_params* best, double* best_ms, void* stream) {
-    if (!lat || !base || !eta_dev || nrhs < 1 || !best || storage_mask < 0 || storage_mask > 7) {
+    if (!lat || !base || !eta_dev || nrhs < 1 || nsrc < 1 || nsrc > 16 || !best || storage_mask < 0 ||
+        storage_mask > 7) {
         wcl_set_error("wcl_autotune: bad argument");
         return WCL_EINVAL;
     }
@@ -121,15 +122,17 @@ extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, dou
     }
     Cand bestc = cur;
     double bms = 1e30;
-    // time = best of two complete solves (the first also warms the workspace),
-    // scaled to the tolerance: t x log(tol) / log(achieved true residual).  A
-    // solve that ends well below the tolerance has bought extra reduction with
-    // its last iteration; ranking by the estimated time to reach the tolerance
-    // itself removes that step of one iteration more or less, which depends on
-    // the source, so the choice carries over to other sources.  A candidate that
-    // needs more than 10 outer iterations is no contender and is dropped, as is
-    // the second solve of one more than 3 x slower than the best
+    // A candidate's time is the sum over the tuning sources of its solve time
+    // (the best of two solves for the first source: the first solve also warms
+    // the workspace), each credited for a solve that ends below the tolerance:
+    // with n inner iterations and f = log(tol) / log(achieved true residual),
+    // geometric convergence would reach the tolerance after f n iterations, but
+    // a new source still pays for whole iterations, so the credit is
+    // min(n (1 - f), 1/2) iterations.  A candidate that needs more than 10
+    // outer iterations is no contender and is dropped, as is one whose time
+    // already exceeds 3 x the best
     const double ltol = std::log(std::min(std::max(base->tol_outer, 1e-300), 0.5));
+    const size_t src_bytes = spinor_rhs_bytes(WCL_F64, lat->V) * nrhs;
     auto measure = [&](const Cand& c0, double* ms) -> bool {
         Blocks B;
         if (make_blocks(lat, &c0.p.ras, &B) != WCL_OK) return false;
@@ -137,21 +140,29 @@ extern "C" int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, dou
         c.p.max_outer = std::min(c.p.max_outer, 10);
         const int saved = lat->lps;
         lat->lps = c.lps;
-        double t = 1e30;
+        double total = 0.0;
         bool ok = true;
-        for (int rep = 0; rep < 2 && ok; ++rep) {
-            wcl_solve_stats s{};
-            int r = nested_solve(lat, ws, &c.p, kappa, csw, eta_dev, phi, nrhs, &s, st);
-            if (r != WCL_OK || !s.converged) ok = false;
-            else {
-                const double lres = std::log(std::max(s.true_resid, 1e-300));
-                const double f = lres < ltol ? ltol / lres : 1.0;
-                t = std::min(t, s.ms_total * f);
+        for (int k = 0; k < nsrc && ok; ++k) {
+            const void* eta = (const char*)eta_dev + k * src_bytes;
+            double t = 1e30;
+            for (int rep = 0; rep < (k == 0 ? 2 : 1) && ok; ++rep) {
+                wcl_solve_stats s{};
+                int r = nested_solve(lat, ws, &c.p, kappa, csw, eta, phi, nrhs, &s, st);
+                if (r != WCL_OK || !s.converged) {
+                    ok = false;
+                } else {
+                    const double n = std::max(1, s.inner_iters);
+                    const double lres = std::log(std::max(s.true_resid, 1e-300));
+                    const double f = lres < ltol ? ltol / lres : 1.0;
+                    const double credit = std::min(n * (1.0 - f), 0.5);
+                    t = std::min(t, s.ms_total * (n - credit) / n);
+                }
+                if (ok && total + t > 3.0 * bms) ok = false;
             }
-            if (ok && t > 3.0 * bms) break;
+            total += t;
         }
         lat->lps = saved;
-        *ms = t;
+        *ms = total;
         return ok;
     };
     auto consider = [&](const Cand& c) {

@@ -350,13 +350,14 @@ class Server:
 
 lib.wcl_autotune.restype = C.c_int
 lib.wcl_autotune.argtypes = [C.c_void_p, C.POINTER(SolverParams), C.c_double, C.c_double, C.c_void_p, C.c_int,
-                             C.c_int, C.c_char_p, C.POINTER(SolverParams), C.POINTER(C.c_double), C.c_void_p]
+                             C.c_int, C.c_int, C.c_char_p, C.POINTER(SolverParams), C.POINTER(C.c_double),
+                             C.c_void_p]
 
 
 def autotune(lat: Lattice, base: SolverParams, kappa: float, csw: float, eta: torch.Tensor, nrhs: int = 1,
-             cache_path: str | None = None, stream=None, storage=None, storage_mask=None):
-    """Autotuned solver parameters for this lattice, timed on the tuning source
-    eta (see include/wcl.h).  storage: None = every candidate, F32 = FP32
+             cache_path: str | None = None, stream=None, storage=None, storage_mask=None, nsrc: int = 1):
+    """Autotuned solver parameters for this lattice, timed on the nsrc tuning
+    sources in eta (nsrc x nrhs FP64 spinors, see include/wcl.h).  storage: None = every candidate, F32 = FP32
     storage only, F16 = FP16 storage with either arithmetic; storage_mask
     (bit 0 FP32, bit 1 FP16, bit 2 FP16 with binary16-operand MR steps)
     overrides it."""
@@ -366,6 +367,6 @@ def autotune(lat: Lattice, base: SolverParams, kappa: float, csw: float, eta: to
         mask = storage_mask
     else:
         mask = 0 if storage is None else (1 if storage == F32 else 6)
-    check(lib.wcl_autotune(lat.h, C.byref(base), kappa, csw, _ptr(eta), nrhs, mask,
+    check(lib.wcl_autotune(lat.h, C.byref(base), kappa, csw, _ptr(eta), nrhs, nsrc, mask,
                            cache_path.encode() if cache_path else None, C.byref(best), C.byref(ms), _stream(stream)))
     return best, ms.value

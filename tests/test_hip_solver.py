@@ -287,3 +287,26 @@ def test_autotune_and_cache(W, ctx, tmp_path):
     assert ms2 == pytest.approx(ms, rel=1e-3)
     assert len(open(cache).read().splitlines()) == 1
     lat.close()
+
+
+def test_autotune_two_sources_and_arith(W, ctx):
+    """Tuning on two sources (nsrc = 2, stored one after the other) picks
+    parameters that solve a third source to tolerance; the cache line keeps
+    the arithmetic of the MR steps; nsrc outside 1..16 is rejected."""
+    dims = (8, 8, 8, 16)
+    U, lat = make(W, ctx, dims)
+    srcs = np.stack([I.gaussian_source(dims, 7), I.gaussian_source(dims, 8)])
+    et = lat.pack(srcs, W.F64, 2)
+    base = W.SolverParams.make()
+    best, ms = W.autotune(lat, base, 0.125, 1.0, et, 1, storage=W.F16, nsrc=2)
+    assert ms > 0 and best.ras.storage == W.F16 and best.ras.arith in (W.ARITH_FP32, W.ARITH_DOT2)
+    eta = I.gaussian_source(dims, 2)
+    phi = lat.zeros(W.F64)
+    rc, st = lat.solve_nested(best, 0.125, 1.0, lat.pack(eta, W.F64), phi)
+    res = np.linalg.norm(eta - Oracle(dims, U).apply_D(lat.unpack(phi, W.F64), 0.125, 1.0)) / np.linalg.norm(eta)
+    assert res <= 1e-10
+    for bad in (0, 17):
+        with pytest.raises(W.WclError) as e:
+            W.autotune(lat, base, 0.125, 1.0, et, 1, nsrc=bad)
+        assert e.value.code == W.EINVAL
+    lat.close()
