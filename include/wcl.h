@@ -264,8 +264,9 @@ int wcl_ras_precondition(wcl_lattice* lat, const wcl_ras_params* ras, double kap
  * process ends) and it calls no allocator.  Only the on-chip path: minimal-
  * residual domain solves inside RAS (block_solver = MR, schwarz = RAS,
  * kernel != SPLIT) with extended domains of at most 256 sites; anything else,
- * or needing more than the fixed size (4 storage-precision fields x nrhs for
- * n_ras >= 3), returns WCL_EINVAL.  Every call on one GPU shares that array,
+ * or needing more than the fixed size (n_ras + 1 storage-precision fields x
+ * nrhs for n_ras >= 3: the kept corrections of all sweeps but the last and
+ * two residuals), returns WCL_EINVAL.  Every call on one GPU shares that array,
  * which keeps the last call's contents (nothing in it needs to start at
  * zero): calls that overlap in time on one GPU (other streams or threads)
  * race and must be serialised by the caller.  Asynchronous on stream. */

@@ -1388,17 +1388,30 @@ __global__ __launch_bounds__(NT, FusedShape<DOT>::min_waves) void k_blk_fused(Bl
 #pragma unroll
         for (int k = 0; k < 24; ++k) xs[k] *= scale;
     }
+    if (write_vj) SpinorIO<VP>::store((char*)a.vj + rhs * a.vj_stride, a.g.V, gi, xs);
+    if (a.skip_out) return;
     char* out = (char*)a.out + rhs * a.out_stride;
-    if (a.accumulate) {
+    if (a.accumulate || a.vsum_n > 0) {
+        // out (+)= the earlier sweeps' corrections, in sweep order, then x
         float o[24];
-        SpinorIO<WCL_F32>::load(out, a.g.V, gi, o);
+        if (a.accumulate) {
+            SpinorIO<WCL_F32>::load(out, a.g.V, gi, o);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 24; ++k) o[k] = 0.f;
+        }
+        for (int j = 0; j < a.vsum_n; ++j) {
+            float t[24];
+            SpinorIO<VP>::load((const char*)a.vsum + j * a.vsum_step + rhs * a.vj_stride, a.g.V, gi, t);
+#pragma unroll
+            for (int k = 0; k < 24; ++k) o[k] += t[k];
+        }
 #pragma unroll
         for (int k = 0; k < 24; ++k) o[k] += xs[k];
         SpinorIO<WCL_F32>::store(out, a.g.V, gi, o);
     } else {
         SpinorIO<WCL_F32>::store(out, a.g.V, gi, xs);
     }
-    if (write_vj) SpinorIO<VP>::store((char*)a.vj + rhs * a.vj_stride, a.g.V, gi, xs);
 }
 
 int fused_threads(int ev) { return ev <= 256 ? 256 : 0; }

@@ -144,6 +144,14 @@ struct BlockArgs {
     double* dsc;         // truncated BiCGStab per-(rhs, domain) scalars [rhs][nblocks][8]:
                          // rho, alpha, omega, rho_old (complex)
     int dot2;            // on-chip MR steps with binary16 operands and FP32 sums (FP16 storage only)
+    // on-chip path, output of the sweeps: skip_out = 1 writes no output (the
+    // sweep's correction goes to vj only); vsum_n > 0 writes
+    // out = vsum[0] + ... + vsum[vsum_n - 1] + x, vsum[j] at vsum + j * vsum_step
+    // (storage precision, per-rhs stride vj_stride)
+    int skip_out;
+    const void* vsum;
+    int vsum_n;
+    size_t vsum_step;
 };
 
 int launch_blk_project(const BlockArgs& a, int src_prec, int bicgstab, hipStream_t st);

@@ -164,7 +164,8 @@ size_t nested_workspace_bytes(const wcl_lattice* lat, const wcl_solver_params* p
     if (prm && prm->precond == WCL_PRECOND_RAS) {
         Blocks B;
         if (make_blocks(lat, &prm->ras, &B) == WCL_OK) {
-            b += 4 * spinor_rhs_bytes(prm->ras.storage, lat->V) * nrhs;   // v_j, r_j ping-pong
+            // kept corrections v_j (NRAS - 1 on chip), residuals r_j (ping-pong)
+            b += (size_t)(std::max(B.n_ras - 1, 2) + 2) * spinor_rhs_bytes(prm->ras.storage, lat->V) * nrhs;
             const bool split = fused_threads(B.ev) != 256 || B.solver != WCL_DOMSOLVE_MR ||
                                B.schwarz != WCL_SCHWARZ_RAS;
             const int nws = B.solver == WCL_DOMSOLVE_BICGSTAB ? 7 : 3;
@@ -314,14 +315,13 @@ static void ras_buffer_list(const Blocks& B, bool fused, int storage, int64_t V,
     const size_t sst = spinor_rhs_bytes(storage, V) * nrhs;
     out.clear();
     if (fused) {
+        // every sweep but the last keeps its correction v_j (one slot each:
+        // the last sweep sums them into the output); the residuals ping-pong
         if (B.n_ras > 1) {
-            out.push_back({"ras.vj", sst, &b.vj[0]});
+            out.push_back({"ras.vj", sst * (B.n_ras - 1), &b.vj[0]});
             out.push_back({"ras.r0", sst, &b.rbuf[0]});
         }
-        if (B.n_ras > 2) {
-            out.push_back({"ras.vj1", sst, &b.vj[1]});
-            out.push_back({"ras.r1", sst, &b.rbuf[1]});
-        }
+        if (B.n_ras > 2) out.push_back({"ras.r1", sst, &b.rbuf[1]});
         return;
     }
     const int T = schwarz_passes(B);
@@ -467,16 +467,23 @@ static int ras_run(wcl_lattice* lat, const Blocks& B, bool fused, int storage, d
     a.vj_stride = sst;
     if (fused) {
         // Between sweeps r_{j+1} = r_j - D v_j: the next sweep's kernel forms
-        // it (v_j ping-pongs, since that kernel reads the neighbours' v_j
-        // while writing its own v_{j+1}).
+        // it from v_j.  phi = sum_j v_j (Algorithm 1) is written once, by the
+        // last sweep, from the kept corrections of the earlier ones (storage
+        // precision) and its own: the output is not read and written again
+        // by every sweep.
+        const size_t slot = sst * nrhs;
         for (int j = 0; j < B.n_ras; ++j) {
             const bool last = j == B.n_ras - 1;
             tl_mark(tl, CAT_DOMINV);
-            a.accumulate = j > 0;
-            a.vprev = j == 0 ? nullptr : bf.vj[(j - 1) % 2];
+            a.accumulate = 0;
+            a.skip_out = !last;
+            a.vsum = bf.vj[0];
+            a.vsum_n = last ? j : 0;
+            a.vsum_step = slot;
+            a.vprev = j == 0 ? nullptr : (const char*)bf.vj[0] + (j - 1) * slot;
             a.vprev_stride = sst;
             a.rout_stride = sst;
-            a.vj = last ? nullptr : bf.vj[j % 2];
+            a.vj = last ? nullptr : (char*)bf.vj[0] + j * slot;
             a.res_boundary = no_overlap;
             int src_prec;
             if (no_overlap) {
@@ -633,9 +640,9 @@ struct Engine {
     int eo = 0;
     const void* eo_ainv = nullptr;
     void* eo_t = nullptr;   // half-field temporary A_oo^{-1} H_oe x
-    // largest |r| / |b| over the active rhs at the start of the current
-    // iteration (what the preconditioner's accuracy is measured against)
-    double rel_now = 1.0;
+    // |r| / |b| of each rhs at the start of the current iteration (what the
+    // preconditioner's accuracy is measured against; 1 before the first)
+    std::vector<double> rel_now;
 
     ~Engine() {
         if (ev) (void)hipEventDestroy(ev);
@@ -749,10 +756,13 @@ struct Engine {
         return WCL_OK;
     }
 
-    // Solves A x = b (A = D at precision gp) for the rhs with act[i] = 1.
+    // Solves A x = b (A = D at precision gp) for the rhs with act[i] = 1, to
+    // |r| <= tol |b| (or tol_rhs[i] |b| per rhs when given).
     // On return act[i] = 1 marks the rhs that converged.
     int run(const void* b, void* x, double tol, int max_iter, const Precond* K, std::vector<int>& act, bool true_check,
-            int max_restarts, EngineResult* res) {
+            int max_restarts, EngineResult* res, const std::vector<double>* tol_rhs = nullptr) {
+        auto tol_of = [&](int i) { return tol_rhs ? (*tol_rhs)[i] : tol; };
+        rel_now.assign(nrhs, 1.0);
         WCL_CHECK(init(K));
         WCL_CHECK(ws->host_scal(tag, nrhs, &h));
         WCL_HIP(hipHostGetDevicePointer((void**)&hmap, h, 0));
@@ -804,9 +814,8 @@ struct Engine {
         bool p_ready = false;
         while (any_active() && it < max_iter) {
             ++it;
-            rel_now = 0.0;
             for (int i = 0; i < nrhs; ++i)
-                if (h[i].active && bnorm[i] > 0) rel_now = std::max(rel_now, std::sqrt(h[i].rr) / bnorm[i]);
+                rel_now[i] = (h[i].active && bnorm[i] > 0) ? std::sqrt(h[i].rr) / bnorm[i] : 0.0;
             ws->tl.mark(CAT_BLAS);
             if (!p_ready) WCL_CHECK(blas_p_update(P, V, nrhs, d, r, p, v, st));
             p_ready = false;
@@ -840,7 +849,7 @@ struct Engine {
                     continue;
                 }
                 const double rel = std::sqrt(rr) / bnorm[i];
-                if (rel <= tol) {
+                if (rel <= tol_of(i)) {
                     if (true_check) {
                         want_true = true;
                         restart[i] = 3;   // candidate
@@ -873,7 +882,7 @@ struct Engine {
                 for (int i = 0; i < nrhs; ++i) {
                     if (restart[i] != 3) continue;
                     const double trel = std::sqrt(h[i].rr) / bnorm[i];
-                    if (trel <= tol) {
+                    if (trel <= tol_of(i)) {
                         h[i].active = 0;
                         conv[i] = 1;
                         tres[i] = trel;
@@ -1122,11 +1131,16 @@ int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, 
         // residual to its target: about tol / (|r| / |b|), with a safety
         // factor of 4; never tighter than tol_inner, never looser than 0.1.
         // (An exact preconditioner would end the outer solve in one step.)
-        const double want = 0.25 * tol / std::max(outer.rel_now, 1e-300);
-        const double tin = std::max(prm->tol_inner, std::min(0.1, want));
+        // Per rhs, so that a batched rhs takes the path of its own solve.
+        std::vector<double> tin(nrhs, prm->tol_inner);
+        for (int i = 0; i < nrhs; ++i) {
+            const double want = 0.25 * tol / std::max(outer.rel_now[i], 1e-300);
+            tin[i] = std::max(prm->tol_inner, std::min(0.1, want));
+        }
         std::vector<int> a = act;
         EngineResult r;
-        WCL_CHECK(inner.run(b32, y32, tin, prm->max_inner, use_ras ? &Kras : nullptr, a, false, 0, &r));
+        WCL_CHECK(inner.run(b32, y32, prm->tol_inner, prm->max_inner, use_ras ? &Kras : nullptr, a, false, 0, &r,
+                            &tin));
         S->inner_iters += r.iters;
         ws->tl.mark(CAT_BLAS);
         WCL_CHECK(blas_to_f64_scaled(Vs, nrhs, sc, y32, out, st));
