@@ -82,11 +82,10 @@ struct SpinorIO<WCL_F64> {
     }
     // the spinor as stored and its scale (1 here): see SpinorIO<WCL_F16>
     using Stored = T;
-    WCL_DEV static T load_u(const void* base, int V, int i, T s[24]) {
+    WCL_DEV static T load_s(const void* base, int V, int i, Stored s[24]) {
         load(base, V, i, s);
         return T(1);
     }
-    WCL_DEV static T load_s(const void* base, int V, int i, Stored s[24]) { return load_u(base, V, i, s); }
     WCL_DEV static void store(void* base, int V, int i, const T s[24]) {
         d2v* p = (d2v*)base;
 #pragma unroll
@@ -112,11 +111,10 @@ struct SpinorIO<WCL_F32> {
         }
     }
     using Stored = T;
-    WCL_DEV static T load_u(const void* base, int V, int i, T s[24]) {
+    WCL_DEV static T load_s(const void* base, int V, int i, Stored s[24]) {
         load(base, V, i, s);
         return T(1);
     }
-    WCL_DEV static T load_s(const void* base, int V, int i, Stored s[24]) { return load_u(base, V, i, s); }
     WCL_DEV static void store(void* base, int V, int i, const T s[24]) {
         f4v* p = (f4v*)base;
 #pragma unroll
@@ -145,20 +143,9 @@ struct SpinorIO<WCL_F16> {
             for (int j = 0; j < 8; ++j) s[8 * g + j] = v[j] * sc;
         }
     }
-    // The stored values (value / scale) widened, without the scale, which is
-    // returned: a linear consumer applies it once to its result.
-    WCL_DEV static T load_u(const void* base, int V, int i, T s[24]) {
-        const h8v* p = (const h8v*)base;
-#pragma unroll
-        for (int g = 0; g < 3; ++g) {
-            f8v v = __builtin_convertvector(p[tix(g, i, 3)], f8v);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) s[8 * g + j] = v[j];
-        }
-        return scale_ptr(base, V)[i];
-    }
-    // The stored binary16 values themselves (consumers widen them inside
-    // mixed-precision FMAs) and the scale.
+    // The stored binary16 values themselves (value / scale; consumers widen
+    // them inside mixed-precision FMAs) and the scale, which is returned: a
+    // linear consumer applies it once to its result.
     using Stored = _Float16;
     WCL_DEV static T load_s(const void* base, int V, int i, _Float16 s[24]) {
         const h8v* p = (const h8v*)base;
