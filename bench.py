@@ -377,10 +377,50 @@ def serve_bench(W, I, np, ctx, n_req, slots):
     opened["rate_per_s"] = round(lam, 3)
     opened["hbm_budget_bytes"] = 24 << 30
     log(f"serving: Poisson p50 {opened['p50_ms']} ms p99 {opened['p99_ms']} ms")
+    shared = serve_shared_config(W, I, np, ctx)
+    log(f"serving: shared configuration {shared['solves_per_s_batched']} solves/s batched, "
+        f"{shared['solves_per_s_unbatched']} unbatched")
     return {"closed_loop": closed, "closed_loop_one_slot": single,
             "overlap_gain": round(closed["solves_per_s"] / single["solves_per_s"], 3), "poisson": opened,
             "slots": slots, "oracle_check": check,
-            "mix": {"x".join(map(str, d)): wt for d, wt in zip(SERVE_SIZES, SERVE_WEIGHTS)}}
+            "mix": {"x".join(map(str, d)): wt for d, wt in zip(SERVE_SIZES, SERVE_WEIGHTS)},
+            "shared_config": shared}
+
+
+def serve_shared_config(W, I, np, ctx, n_req=48, max_batch=12):
+    """Many sources on one configuration (the usual lattice workload): 48
+    requests on 16^3x32 (eps 0.5, seed 1) with kappa 0.125, c_sw 1.0 and
+    Gaussian sources (seed 4000 + request id), all submitted at once to one
+    slot, without merging and with up to 12 requests per solve.  Results are
+    compared bitwise between the two runs, one is checked by the oracle."""
+    d = (16, 16, 16, 32)
+    U = I.random_gauge(d, 0.5, 1)
+    sources = [I.gaussian_source(d, 4000 + i) for i in range(n_req)]
+
+    def run(mb):
+        srv = W.Server(ctx, max_slots=1, max_batch=mb)
+        srv.register_gauge(0, d, U)
+        t = srv.submit(0, 0.125, 1.0, sources[0])   # warm the slot's workspace
+        srv.wait(t)
+        t0 = time.monotonic()
+        tickets = [srv.submit(0, 0.125, 1.0, src) for src in sources]
+        out = [srv.wait(t) for t in tickets]
+        T = time.monotonic() - t0
+        srv.close()
+        return out, T
+
+    alone, t1 = run(1)
+    batched, tb = run(max_batch)
+    same = all(np.array_equal(a[0], b[0]) for a, b in zip(alone, batched))
+    ok = all(r["status"] == 0 and r["true_resid"] <= 1e-10 for _, r in batched)
+    from oracle import Oracle
+    o = Oracle(d, U, precompute_clover=False)
+    res = float(np.linalg.norm(sources[5] - o.apply_D(batched[5][0], 0.125, 1.0)) / np.linalg.norm(sources[5]))
+    sizes = [r["batch"] for _, r in batched]
+    return {"lattice": list(d), "requests": n_req, "max_batch": max_batch,
+            "solves_per_s_unbatched": round(n_req / t1, 3), "solves_per_s_batched": round(n_req / tb, 3),
+            "batching_gain": round(t1 / tb, 3), "batch_sizes_seen": sorted(set(sizes)),
+            "results_bitwise_equal": same, "all_converged": ok, "true_resid_by_oracle_request_5": res}
 
 
 def roofline_alu(achieved_tflops, kernel, us, traffic, flops):

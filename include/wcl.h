@@ -323,13 +323,18 @@ int wcl_autotune(wcl_lattice* lat, const wcl_solver_params* base, double kappa, 
  * max_slots worker slots, each with its own HIP stream and solver workspace.
  * Requests wait in FIFO order and are admitted as soon as a slot is free and
  * the HBM they need fits the budget; admitted requests run concurrently on
- * the device.  Each result is identical (bitwise) to the same solve run
- * alone: a solve's arithmetic does not depend on the other requests.
- * wcl_submit and wcl_poll are thread-safe. */
+ * the device.  With max_batch > 1 the request at the head of the queue takes
+ * along up to max_batch - 1 queued requests that have the same configuration,
+ * kappa, c_sw and solver parameters: they are solved together as the
+ * right-hand sides of one nested solve (Sec. 3, every kernel batched over the
+ * rhs), so they share every launch.  Each result is identical (bitwise) to
+ * the same solve run alone, batched or not: a solve's arithmetic does not
+ * depend on the other requests.  wcl_submit and wcl_poll are thread-safe. */
 typedef struct wcl_server_params {
     uint64_t hbm_budget_bytes;  /* total for fields + workspaces; 0 = the context budget */
     int max_slots;              /* concurrent solves (>= 1) */
     int max_queue;              /* waiting requests before WCL_ENOMEM (0 = 4096) */
+    int max_batch;              /* requests merged into one solve (0 or 1 = none, at most 64) */
 } wcl_server_params;
 
 typedef struct wcl_request {
@@ -342,8 +347,10 @@ typedef struct wcl_request {
 
 typedef struct wcl_result {
     int status;                 /* WCL_OK or the solver's error code */
-    wcl_solve_stats stats;
+    wcl_solve_stats stats;      /* of the solve; for a batch: its counters and times, and this request's own
+                                   true residual and convergence */
     double t_submit, t_admit, t_done;   /* seconds, steady clock */
+    int batch;                  /* requests solved together with this one, itself included (1 = alone) */
 } wcl_result;
 
 int wcl_server_create(wcl_ctx* ctx, const wcl_server_params* p, wcl_server** srv);

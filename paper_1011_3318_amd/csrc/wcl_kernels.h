@@ -178,8 +178,11 @@ void wcl_workspace_delete(Workspace* w);
 size_t workspace_bytes(const Workspace* w);
 void workspace_get(Workspace* w, const char* name, size_t bytes, void** out, int* rc);
 // Nested RAS-BiCGStab on an explicit workspace and stream (Sec. 3).
+// resid_rhs (optional, nrhs values): |eta_i - D phi_i| / |eta_i| per rhs
+// (0 for a zero rhs, -1 where the solve ended on a hard error).
 int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, double kappa, double csw,
-                 const void* eta, void* phi, int nrhs, wcl_solve_stats* stats, hipStream_t st);
+                 const void* eta, void* phi, int nrhs, wcl_solve_stats* stats, hipStream_t st,
+                 double* resid_rhs = nullptr);
 // Device bytes a nested solve needs on a fresh workspace (estimate, upper bound).
 size_t nested_workspace_bytes(const wcl_lattice* lat, const wcl_solver_params* prm, int nrhs);
 int fused_threads(int ev);   // workgroup size of the fused domain solver, 0 if it does not fit

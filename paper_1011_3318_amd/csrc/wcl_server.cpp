@@ -1,16 +1,21 @@
-// Serving loop: continuous batching of nested-solver requests on one device.
+// Serving loop: continuous batching of nested-solve requests on one device.
 //
 // Each registered gauge configuration stays resident (links + clover).  A
 // request waits in a FIFO queue until a slot is free and the device memory
 // its solve needs fits the budget; then the slot's worker thread runs it on
 // the slot's own HIP stream with the slot's own workspace, so admitted
-// requests overlap on the device.  A slot keeps its workspace between
-// requests (no device allocation on the hot path once warm); admission
-// (admit_decide in wcl_admit.h) keeps every workspace while the budget
-// allows and releases idle ones only when a request would not fit.
+// requests overlap on the device.  Queued requests with the same
+// configuration, kappa, c_sw and solver parameters as the head of the queue
+// join its solve as further right-hand sides (up to max_batch), so they
+// share every launch; a batched right-hand side gives bitwise the result of
+// its own solve.  A slot keeps its workspace between requests (no device
+// allocation on the hot path once warm); admission (admit_decide in
+// wcl_admit.h) keeps every workspace while the budget allows and releases
+// idle ones only when a request would not fit.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cstring>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -34,8 +39,8 @@ struct Job {
     wcl_solver_params params{};
     wcl_lattice* lat = nullptr;
     size_t need = 0;       // estimated workspace bytes of the solve
-    size_t reserved = 0;   // bytes charged at admission
     uint64_t key = 0;      // lattice and solver parameters the workspace is built for
+    uint64_t bkey = 0;     // requests with equal bkey can share one solve
     double t_submit = 0, t_admit = 0;
 };
 
@@ -56,6 +61,34 @@ uint64_t job_key(const wcl_lattice* lat, const wcl_solver_params& p) {
     return h | 1;   // never 0
 }
 
+uint64_t dbits(double v) {
+    uint64_t b;
+    std::memcpy(&b, &v, sizeof b);
+    return b;
+}
+
+// FNV-1a over everything that defines the operator and the solve: requests
+// with the same value solve the same system up to their sources
+uint64_t batch_key(const wcl_lattice* lat, const wcl_request& r, const wcl_solver_params& p) {
+    uint64_t h = job_key(lat, p);
+    auto mix = [&](uint64_t v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (v >> (8 * k)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    mix(dbits(r.kappa));
+    mix(dbits(r.csw));
+    mix(dbits(p.tol_outer));
+    mix(dbits(p.tol_inner));
+    const int f[] = {p.max_outer, p.max_inner, p.max_restarts, p.timers, p.ras.arith};
+    for (int v : f) mix((uint64_t)(uint32_t)v);
+    return h | 1;
+}
+
+// workspace key of a solve of nrhs right-hand sides
+uint64_t nrhs_key(uint64_t key, int nrhs) { return (key ^ (0x9e3779b97f4a7c15ull * (uint64_t)nrhs)) | 1; }
+
 // default RAS domain: 4 in every direction it divides, else 2, else the extent
 int default_block(int L) { return L % 4 == 0 ? 4 : (L % 2 == 0 ? 2 : L); }
 
@@ -65,6 +98,7 @@ struct wcl_server {
     wcl_ctx* ctx = nullptr;
     uint64_t budget = 0;
     int max_queue = 4096;
+    int max_batch = 1;
     std::map<uint64_t, wcl_lattice*> configs;
     std::mutex mu;
     std::condition_variable cv_done;
@@ -76,7 +110,8 @@ struct wcl_server {
         size_t held = 0;    // bytes the slot's workspace holds
         uint64_t key = 0;   // what that workspace was built for
         bool busy = false;
-        Job job;
+        std::vector<Job> jobs;   // the requests of the current solve (one rhs each)
+        size_t reserved = 0;     // bytes charged at its admission
         std::condition_variable cv;
     };
     std::vector<Slot*> slots;
@@ -105,64 +140,117 @@ struct wcl_server {
         s->key = 0;
     }
 
+    // device bytes of one solve of n requests like j (workspace, sources,
+    // solutions and the host staging buffer)
+    static size_t batch_need(const Job& j, int n) {
+        return nested_workspace_bytes(j.lat, &j.params, n) + 2 * spinor_rhs_bytes(WCL_F64, j.lat->V) * n +
+               (size_t)j.lat->V * 24 * sizeof(double);
+    }
+
     // Admits queued requests in FIFO order while a slot is free and the
-    // budget allows (admit_decide).  Called with mu held.
+    // budget allows (admit_decide).  The head of the queue takes along the
+    // queued requests with its batch key, up to max_batch, when that batch
+    // fits; otherwise it goes alone.  Called with mu held.
     void admit() {
         while (!queue.empty()) {
             std::vector<AdmitSlot> st;
             for (auto* s : slots) st.push_back(AdmitSlot{s->busy, s->held, s->key});
-            Job& j = queue.front();
-            const AdmitDecision d = admit_decide(st, budget, resident_bytes(), reserved, j.need, j.key);
+            const Job& head = queue.front();
+            std::vector<size_t> pick = {0};
+            for (size_t q = 1; q < queue.size() && (int)pick.size() < max_batch; ++q)
+                if (queue[q].bkey == head.bkey) pick.push_back(q);
+            AdmitDecision d{};
+            d.slot = -1;
+            while (!pick.empty()) {
+                const int n = (int)pick.size();
+                d = admit_decide(st, budget, resident_bytes(), reserved, n == 1 ? head.need : batch_need(head, n),
+                                 n == 1 ? head.key : nrhs_key(head.key, n));
+                if (d.slot >= 0 || n == 1) break;
+                pick.resize(1);   // the batch does not fit now: try the head alone
+            }
             if (d.slot < 0) return;   // head of line waits for a slot or for memory
             Slot* free_slot = slots[d.slot];
             if (d.release_idle)
                 for (auto* s : slots)
                     if (!s->busy && s != free_slot && s->held) release_workspace(s);
             if (d.release_slot) release_workspace(free_slot);
-            Job job = j;
-            queue.pop_front();
-            job.reserved = d.charge;
-            job.t_admit = now_s();
+            const int n = (int)pick.size();
+            const double t = now_s();
+            free_slot->jobs.clear();
+            for (size_t q : pick) {
+                free_slot->jobs.push_back(queue[q]);
+                free_slot->jobs.back().t_admit = t;
+            }
+            for (size_t k = pick.size(); k-- > 0;) queue.erase(queue.begin() + (ptrdiff_t)pick[k]);
+            free_slot->reserved = d.charge;
             reserved += d.charge;
-            free_slot->key = job.key;
-            free_slot->job = job;
+            free_slot->key = n == 1 ? free_slot->jobs[0].key : nrhs_key(free_slot->jobs[0].key, n);
             free_slot->busy = true;
             free_slot->cv.notify_one();
         }
     }
 
+    // One nested solve with the slot's requests as its right-hand sides.
     void run_job(Slot* s) {
-        Job& j = s->job;
-        wcl_result res{};
-        res.t_submit = j.t_submit;
-        res.t_admit = j.t_admit;
+        const std::vector<Job>& js = s->jobs;
+        const Job& j = js[0];
+        const int n = (int)js.size();
+        wcl_solve_stats stats{};
+        std::vector<double> resid(n, -1.0);
         int rc = WCL_OK;
         const int64_t V = j.lat->V;
         const size_t b64 = spinor_rhs_bytes(WCL_F64, V), stage_b = (size_t)V * 24 * sizeof(double);
         void *eta = nullptr, *phi = nullptr, *stage = nullptr;
-        workspace_get(s->ws, "srv.eta", b64, &eta, &rc);
-        if (rc == WCL_OK) workspace_get(s->ws, "srv.phi", b64, &phi, &rc);
+        workspace_get(s->ws, "srv.eta", b64 * n, &eta, &rc);
+        if (rc == WCL_OK) workspace_get(s->ws, "srv.phi", b64 * n, &phi, &rc);
         if (rc == WCL_OK) workspace_get(s->ws, "srv.stage", stage_b, &stage, &rc);
-        if (rc == WCL_OK && hipMemcpyAsync(stage, j.req.eta_host, stage_b, hipMemcpyHostToDevice, s->st) != hipSuccess)
-            rc = WCL_EHIP;
-        if (rc == WCL_OK) rc = launch_pack_spinor(j.lat->g, WCL_F64, 1, (const double*)stage, eta, b64, s->st);
+        // the host sources go through one staging buffer, one after the other
+        // (stream order keeps each copy behind the previous pack)
+        for (int k = 0; k < n && rc == WCL_OK; ++k) {
+            if (hipMemcpyAsync(stage, js[k].req.eta_host, stage_b, hipMemcpyHostToDevice, s->st) != hipSuccess)
+                rc = WCL_EHIP;
+            if (rc == WCL_OK)
+                rc = launch_pack_spinor(j.lat->g, WCL_F64, 1, (const double*)stage, (char*)eta + k * b64, b64, s->st);
+        }
         if (rc == WCL_OK)
-            rc = nested_solve(j.lat, s->ws, &j.params, j.req.kappa, j.req.csw, eta, phi, 1, &res.stats, s->st);
+            rc = nested_solve(j.lat, s->ws, &j.params, j.req.kappa, j.req.csw, eta, phi, n, &stats, s->st,
+                              resid.data());
         if (rc == WCL_OK || rc == WCL_ENOTCONV) {
-            int rc2 = launch_unpack_spinor(j.lat->g, WCL_F64, 1, phi, b64, (double*)stage, s->st);
-            if (rc2 == WCL_OK &&
-                hipMemcpyAsync(j.req.phi_host, stage, stage_b, hipMemcpyDeviceToHost, s->st) != hipSuccess)
-                rc2 = WCL_EHIP;
+            int rc2 = WCL_OK;
+            for (int k = 0; k < n && rc2 == WCL_OK; ++k) {
+                rc2 = launch_unpack_spinor(j.lat->g, WCL_F64, 1, (const char*)phi + k * b64, b64, (double*)stage,
+                                           s->st);
+                if (rc2 == WCL_OK &&
+                    hipMemcpyAsync(js[k].req.phi_host, stage, stage_b, hipMemcpyDeviceToHost, s->st) != hipSuccess)
+                    rc2 = WCL_EHIP;
+            }
             if (rc2 == WCL_OK && hipStreamSynchronize(s->st) != hipSuccess) rc2 = WCL_EHIP;
             if (rc2 != WCL_OK) rc = rc2;
         }
-        res.status = rc;
-        res.t_done = now_s();
+        const double t_done = now_s();
         std::lock_guard<std::mutex> g(mu);
-        reserved -= j.reserved;
+        for (int k = 0; k < n; ++k) {
+            wcl_result res{};
+            res.t_submit = js[k].t_submit;
+            res.t_admit = js[k].t_admit;
+            res.t_done = t_done;
+            res.batch = n;
+            res.stats = stats;
+            if (n > 1) {
+                // the batch's counters, this request's own residual and status
+                res.stats.true_resid = resid[k];
+                res.stats.converged = rc == WCL_OK || (rc == WCL_ENOTCONV && resid[k] >= 0 &&
+                                                       resid[k] <= js[k].params.tol_outer);
+                res.status = rc == WCL_ENOTCONV && res.stats.converged ? WCL_OK : rc;
+            } else {
+                res.status = rc;
+            }
+            done[js[k].ticket] = res;
+        }
+        reserved -= s->reserved;
+        s->reserved = 0;
         s->held = workspace_bytes(s->ws);
         s->busy = false;
-        done[j.ticket] = res;
         cv_done.notify_all();
         admit();
     }
@@ -183,7 +271,8 @@ struct wcl_server {
 extern "C" {
 
 int wcl_server_create(wcl_ctx* ctx, const wcl_server_params* p, wcl_server** out) {
-    if (!ctx || !p || !out || p->max_slots < 1 || p->max_slots > 64 || p->max_queue < 0) {
+    if (!ctx || !p || !out || p->max_slots < 1 || p->max_slots > 64 || p->max_queue < 0 || p->max_batch < 0 ||
+        p->max_batch > 64) {
         wcl_set_error("wcl_server_create: bad argument");
         return WCL_EINVAL;
     }
@@ -193,6 +282,7 @@ int wcl_server_create(wcl_ctx* ctx, const wcl_server_params* p, wcl_server** out
     srv->ctx = ctx;
     srv->budget = p->hbm_budget_bytes ? p->hbm_budget_bytes : ctx->budget;
     srv->max_queue = p->max_queue ? p->max_queue : 4096;
+    srv->max_batch = p->max_batch > 1 ? p->max_batch : 1;
     for (int k = 0; k < p->max_slots; ++k) {
         auto* s = new wcl_server::Slot;
         if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess) {
@@ -304,6 +394,7 @@ int wcl_submit(wcl_server* srv, const wcl_request* req, uint64_t* ticket) {
     j.need = nested_workspace_bytes(j.lat, &j.params, 1) + 2 * spinor_rhs_bytes(WCL_F64, j.lat->V) +
              (size_t)j.lat->V * 24 * sizeof(double);
     j.key = job_key(j.lat, j.params);
+    j.bkey = batch_key(j.lat, j.req, j.params);
     if (srv->resident_bytes() + j.need > srv->budget) {
         wcl_set_error("wcl_submit: request needs %llu bytes, more than the budget leaves",
                       (unsigned long long)j.need);

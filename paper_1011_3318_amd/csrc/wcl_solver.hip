@@ -613,6 +613,7 @@ struct EngineResult {
     bool converged = false;
     bool breakdown = false;    // some rhs was dropped for a persistent breakdown
     double true_resid = 0.0;   // max over rhs (only with true_check)
+    std::vector<double> tres;  // per rhs (only with true_check; 0 for a zero rhs)
 };
 
 struct Engine {
@@ -971,8 +972,12 @@ struct Engine {
                     if (h[i].active) tres[i] = std::sqrt(h[i].rr) / bnorm[i];
             }
             res->true_resid = 0.0;
+            res->tres.assign(nrhs, 0.0);
             for (int i = 0; i < nrhs; ++i)
-                if (bnorm[i] > 0) res->true_resid = std::max(res->true_resid, tres[i]);
+                if (bnorm[i] > 0) {
+                    res->true_resid = std::max(res->true_resid, tres[i]);
+                    res->tres[i] = tres[i];
+                }
         }
         return WCL_OK;
     }
@@ -1045,7 +1050,7 @@ static int need_even_extents(const wcl_lattice* lat) {
 // even half fields; phi_o is reconstructed afterwards and the reported true
 // residual is |eta - D phi| / |eta| of the full system.
 int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, double kappa, double csw,
-                 const void* eta, void* phi, int nrhs, wcl_solve_stats* stats, hipStream_t st) {
+                 const void* eta, void* phi, int nrhs, wcl_solve_stats* stats, hipStream_t st, double* resid_rhs) {
     WCL_CHECK(check_solver_params(prm));
     WCL_CHECK(need_fields(lat));
     if (!eta || !phi || nrhs < 1 || !std::isfinite(kappa) || !std::isfinite(csw)) {
@@ -1077,7 +1082,9 @@ int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, 
     // even-odd: b_e = eta_e - H_eo A_oo^{-1} eta_o, solved for x_e
     const void* rhs_vec = eta;
     void* sol_vec = phi;
-    double tol = prm->tol_outer;
+    const double tol = prm->tol_outer;
+    // per-rhs outer tolerance (the even-odd system measures against |b_e|)
+    std::vector<double> tol_rhs(nrhs, tol);
     std::vector<double> eta2;
     if (eo) {
         void* inv[3];
@@ -1109,7 +1116,7 @@ int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, 
         WCL_CHECK(host_norms2(ws, WCL_F64, lat->V, nrhs, eta, st, eta2));
         WCL_CHECK(host_norms2(ws, WCL_F64, Vs, nrhs, be, st, b2));
         for (int i = 0; i < nrhs; ++i)
-            if (b2[i] > 0 && eta2[i] > 0) tol = std::min(tol, prm->tol_outer * std::sqrt(eta2[i] / b2[i]));
+            if (b2[i] > 0 && eta2[i] > 0) tol_rhs[i] = prm->tol_outer * std::sqrt(eta2[i] / b2[i]);
         rhs_vec = be;
         sol_vec = xe;
     }
@@ -1134,7 +1141,7 @@ int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, 
         // Per rhs, so that a batched rhs takes the path of its own solve.
         std::vector<double> tin(nrhs, prm->tol_inner);
         for (int i = 0; i < nrhs; ++i) {
-            const double want = 0.25 * tol / std::max(outer.rel_now[i], 1e-300);
+            const double want = 0.25 * tol_rhs[i] / std::max(outer.rel_now[i], 1e-300);
             tin[i] = std::max(prm->tol_inner, std::min(0.1, want));
         }
         std::vector<int> a = act;
@@ -1148,7 +1155,7 @@ int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, 
     };
     std::vector<int> act(nrhs, 1);
     EngineResult res;
-    int rc = outer.run(rhs_vec, sol_vec, tol, prm->max_outer, &Kinner, act, true, prm->max_restarts, &res);
+    int rc = outer.run(rhs_vec, sol_vec, tol, prm->max_outer, &Kinner, act, true, prm->max_restarts, &res, &tol_rhs);
     if (rc == WCL_OK && eo) {
         // phi_o = A_oo^{-1} (eta_o - H_oe x_e), phi_e = x_e; then the full
         // system's true residual
@@ -1184,9 +1191,15 @@ int nested_solve(wcl_lattice* lat, Workspace* ws, const wcl_solver_params* prm, 
         ws->tl.mark(CAT_BLAS);
         WCL_CHECK(host_norms2(ws, WCL_F64, lat->V, nrhs, rfull, st, r2));
         res.true_resid = 0.0;
+        res.tres.assign(nrhs, 0.0);
         for (int i = 0; i < nrhs; ++i)
-            if (eta2[i] > 0) res.true_resid = std::max(res.true_resid, std::sqrt(r2[i] / eta2[i]));
+            if (eta2[i] > 0) {
+                res.tres[i] = std::sqrt(r2[i] / eta2[i]);
+                res.true_resid = std::max(res.true_resid, res.tres[i]);
+            }
     }
+    if (resid_rhs)
+        for (int i = 0; i < nrhs; ++i) resid_rhs[i] = i < (int)res.tres.size() ? res.tres[i] : -1.0;
     WCL_HIP(hipEventRecord(e1, st));
     WCL_HIP(hipEventSynchronize(e1));
     float ms = 0;

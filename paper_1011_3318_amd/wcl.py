@@ -258,7 +258,8 @@ class Lattice:
 
 # ------------------------------------------------------------------ serving
 class ServerParams(C.Structure):
-    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_slots", C.c_int), ("max_queue", C.c_int)]
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_slots", C.c_int), ("max_queue", C.c_int),
+                ("max_batch", C.c_int)]
 
 
 class Request(C.Structure):
@@ -269,7 +270,7 @@ class Request(C.Structure):
 
 class Result(C.Structure):
     _fields_ = [("status", C.c_int), ("stats", SolveStats), ("t_submit", C.c_double), ("t_admit", C.c_double),
-                ("t_done", C.c_double)]
+                ("t_done", C.c_double), ("batch", C.c_int)]
 
 
 def _server_sigs():
@@ -294,9 +295,11 @@ _server_sigs()
 class Server:
     """Continuous-batching solve server (see include/wcl.h)."""
 
-    def __init__(self, ctx: Context, max_slots: int = 4, hbm_budget: int = 0, max_queue: int = 0):
+    def __init__(self, ctx: Context, max_slots: int = 4, hbm_budget: int = 0, max_queue: int = 0,
+                 max_batch: int = 1):
         h = C.c_void_p()
-        check(lib.wcl_server_create(ctx.h, C.byref(ServerParams(hbm_budget, max_slots, max_queue)), C.byref(h)))
+        check(lib.wcl_server_create(ctx.h, C.byref(ServerParams(hbm_budget, max_slots, max_queue, max_batch)),
+                                    C.byref(h)))
         self.h = h
         self._live = {}   # ticket -> (eta, phi, params) kept alive until collected
         self.dims = {}
@@ -324,7 +327,8 @@ class Server:
 
     def _collect(self, ticket, res):
         eta, phi, _ = self._live.pop(ticket)
-        d = {"status": res.status, "t_submit": res.t_submit, "t_admit": res.t_admit, "t_done": res.t_done}
+        d = {"status": res.status, "t_submit": res.t_submit, "t_admit": res.t_admit, "t_done": res.t_done,
+             "batch": res.batch}
         d.update(res.stats.as_dict())
         return phi, d
 

@@ -153,3 +153,45 @@ def test_mixed_sizes_under_a_tight_budget_drain(W, ctx):
     assert not pending, f"{len(pending)} requests never finished"
     assert all(r["status"] == 0 and r["converged"] == 1 for r in results.values())
     srv.close()
+
+
+def test_batched_requests_equal_alone(W, ctx):
+    """With max_batch > 1, queued requests that share configuration, kappa,
+    c_sw and solver parameters are solved together as the right-hand sides
+    of one solve; requests with another kappa are not merged with them.
+    Every result is bitwise the one the request gets alone, reports its own
+    true residual (oracle-checked), and some solve really held several."""
+    d = CONFIGS[1]
+    U = I.random_gauge(d, 0.5, 1)
+    reqs = [(0.124, 1.0, 2000 + k) for k in range(7)] + [(0.121, 1.5, 3000), (0.124, 1.0, 2007)]
+    alone = []
+    srv = W.Server(ctx, max_slots=1)
+    srv.register_gauge(1, d, U)
+    for kappa, csw, seed in reqs:
+        phi, st = srv.wait(srv.submit(1, kappa, csw, I.gaussian_source(d, seed)))
+        assert st["status"] == 0 and st["batch"] == 1
+        alone.append(phi)
+    srv.close()
+    srv = W.Server(ctx, max_slots=1, max_batch=4)
+    srv.register_gauge(1, d, U)
+    tickets = [srv.submit(1, kappa, csw, I.gaussian_source(d, seed)) for kappa, csw, seed in reqs]
+    got = [srv.wait(t) for t in tickets]
+    srv.close()
+    o = Oracle(d, U)
+    for k, ((phi, st), ref) in enumerate(zip(got, alone)):
+        assert st["status"] == 0 and st["converged"] == 1, k
+        assert np.array_equal(phi, ref), k
+        kappa, csw, seed = reqs[k]
+        eta = I.gaussian_source(d, seed)
+        res = np.linalg.norm(eta - o.apply_D(phi, kappa, csw)) / np.linalg.norm(eta)
+        assert res <= 1e-10 and abs(st["true_resid"] - res) <= 1e-12, k
+    assert max(st["batch"] for _, st in got) > 1
+    assert got[7][1]["batch"] == 1   # the only request with its kappa and c_sw
+    assert all(st["batch"] <= 4 for _, st in got)
+
+
+def test_server_rejects_bad_batch(W, ctx):
+    for bad in (-1, 65):
+        with pytest.raises(W.WclError) as e:
+            W.Server(ctx, max_slots=1, max_batch=bad)
+        assert e.value.code == W.EINVAL
