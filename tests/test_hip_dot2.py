@@ -171,3 +171,27 @@ def test_dot2_rejects_what_it_cannot_run(W, ctx, kw):
         lat.ras_precondition(ras, 0.12, 1.0, lat.zeros(W.F32), lat.empty(W.F32))
     assert e.value.code == W.EINVAL
     lat.close()
+
+
+def test_nested_dot2_batch_equals_single(W, ctx):
+    """A batched dot2 solve (two rhs per workgroup in the domain solver, an
+    odd count so the last workgroup holds one) gives every rhs bitwise its
+    single-rhs solution, each to an oracle true residual <= 1e-10."""
+    dims = (8, 8, 8, 8)
+    kappa, csw = 0.125, 1.0
+    U, lat = make(W, ctx, dims)
+    _, pts = I.point_sources(dims, 3)
+    eta = np.stack([I.gaussian_source(dims, 2), pts[4], I.gaussian_source(dims, 9)])
+    p = W.SolverParams.make(ras=W.RasParams.make(block=(4, 4, 4, 4), s=0, n_ras=3, n_dominv=4, storage=W.F16,
+                                                 arith=W.ARITH_DOT2))
+    phi = lat.zeros(W.F64, 3)
+    rc, st = lat.solve_nested(p, kappa, csw, lat.pack(eta, W.F64, 3), phi, nrhs=3)
+    sols = lat.unpack(phi, W.F64, 3)
+    o = Oracle(dims, U)
+    for k in range(3):
+        res = np.linalg.norm(eta[k] - o.apply_D(sols[k], kappa, csw)) / np.linalg.norm(eta[k])
+        assert res <= 1e-10, (k, res)
+        phi1 = lat.zeros(W.F64)
+        lat.solve_nested(p, kappa, csw, lat.pack(eta[k], W.F64), phi1)
+        assert np.array_equal(lat.unpack(phi1, W.F64), sols[k]), k
+    lat.close()
