@@ -174,9 +174,9 @@ def test_dot2_rejects_what_it_cannot_run(W, ctx, kw):
 
 
 def test_nested_dot2_batch_equals_single(W, ctx):
-    """A batched dot2 solve (two rhs per workgroup in the domain solver, an
-    odd count so the last workgroup holds one) gives every rhs bitwise its
-    single-rhs solution, each to an oracle true residual <= 1e-10."""
+    """A batched dot2 solve (a Gaussian, a point and another Gaussian source)
+    gives every rhs bitwise its single-rhs solution, each to an oracle true
+    residual <= 1e-10."""
     dims = (8, 8, 8, 8)
     kappa, csw = 0.125, 1.0
     U, lat = make(W, ctx, dims)
