@@ -917,6 +917,42 @@ WCL_DEV float dot2n(h2v a, h2v b, float c) {
     return d;
 }
 WCL_DEV h2v pack2(float x, float y) { return h2v{(_Float16)x, (_Float16)y}; }
+// (im, re) of a pair, and i z = (-im, re): the compiler folds both into the
+// operand modifiers of the packed binary16 add that uses them
+WCL_DEV h2v swp(h2v z) { return __builtin_shufflevector(z, z, 1, 0); }
+WCL_DEV h2v mul_i(h2v z) {
+    const h2v t = swp(z);
+    return h2v{-t.x, t.y};
+}
+
+// spin_project on a spinor held as 12 binary16 pairs (u0, u1, l0, l1 by
+// colour), in packed binary16 additions: hp = the half-spinor (h0, h1) as
+// pairs, hs the same pairs swapped (the operands of the v_dot2 products).
+template <int MU, bool FWD>
+WCL_DEV void spin_project16(const h2v s[12], h2v hp[6], h2v hs[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const h2v u0 = s[c], u1 = s[3 + c], l0 = s[6 + c], l1 = s[9 + c];
+        h2v h0, h1;
+        if (MU == 0) {   // h0 = u0 +- i l1, h1 = u1 +- i l0
+            h0 = FWD ? u0 + mul_i(l1) : u0 - mul_i(l1);
+            h1 = FWD ? u1 + mul_i(l0) : u1 - mul_i(l0);
+        } else if (MU == 1) {   // h0 = u0 +- l1, h1 = u1 -+ l0
+            h0 = FWD ? u0 + l1 : u0 - l1;
+            h1 = FWD ? u1 - l0 : u1 + l0;
+        } else if (MU == 2) {   // h0 = u0 +- i l0, h1 = u1 -+ i l1
+            h0 = FWD ? u0 + mul_i(l0) : u0 - mul_i(l0);
+            h1 = FWD ? u1 - mul_i(l1) : u1 + mul_i(l1);
+        } else {   // h = u +- l
+            h0 = FWD ? u0 + l0 : u0 - l0;
+            h1 = FWD ? u1 + l1 : u1 - l1;
+        }
+        hp[c] = h0;
+        hp[3 + c] = h1;
+        hs[c] = swp(h0);
+        hs[3 + c] = swp(h1);
+    }
+}
 
 // FP16 storage with binary16 operands inside the MR steps: the fields as in
 // SiteFields<WCL_F16> (row 2 of each link rebuilt in FP32 at load and
@@ -1049,6 +1085,11 @@ struct SiteFieldsDot {
             hp[k] = pack2(h[2 * k], h[2 * k + 1]);
             hs[k] = pack2(h[2 * k + 1], h[2 * k]);
         }
+        apply16<MU, DAG>(hp, hs, w);
+    }
+    // w = U h or U^dag h for h given as binary16 pairs hp and swapped pairs hs
+    template <int MU, bool DAG>
+    WCL_DEV void apply16(const h2v hp[6], const h2v hs[6], float w[12]) const {
 #pragma unroll
         for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
@@ -1070,6 +1111,13 @@ struct SiteFieldsDot {
             }
     }
     WCL_DEV void step_site_term(const float r[24], float ck, float q[24]) const {
+        h2v rp[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) rp[k] = pack2(r[2 * k], r[2 * k + 1]);
+        site_term16(rp, r, ck, q);
+    }
+    // q = r + ck C r with the products on rp (r as binary16 pairs)
+    WCL_DEV void site_term16(const h2v rp[12], const float r[24], float ck, float q[24]) const {
         const float f = ck * cs;
 #pragma unroll
         for (int bk = 0; bk < 2; ++bk) {
@@ -1078,8 +1126,8 @@ struct SiteFieldsDot {
             h2v xp[6], xs[6];
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
-                xp[k] = pack2(x[2 * k], x[2 * k + 1]);
-                xs[k] = pack2(x[2 * k + 1], x[2 * k]);
+                xp[k] = rp[6 * bk + k];
+                xs[k] = swp(xp[k]);
             }
             float y[12];
 #pragma unroll
@@ -1119,13 +1167,14 @@ struct FusedFields<WCL_F16, true> {
 // RES: 0 = no residual update (first sweep); 1 = r_j = src - D vprev from
 // all eight hops; 2 = r_j = src - (the hops of D vprev that leave the
 // domain), src being the previous sweep's final MR residual (no overlap).
-// DOT: the published backward terms are binary16 pairs (48 instead of 72
-// LDS words per site).  Three domains per CU would then fit the LDS but not
-// the registers: forced to 168 VGPRs the kernel spills and runs slower
-// (measured 850 against 770 us per 32^4 RAS application), so it keeps two.
+// DOT: each site keeps its own rho in registers and publishes it to the
+// neighbours as binary16 pairs, with the backward terms as binary16 pairs
+// (36 instead of 72 LDS words per site).  Three domains per CU would then
+// fit the LDS but not the registers: forced to 168 VGPRs the kernel spills
+// and ran slower, so it keeps two.
 template <bool DOT>
 struct FusedShape {
-    static constexpr int lds_words = DOT ? 48 : 72;
+    static constexpr int lds_words = DOT ? 36 : 72;
     static constexpr int min_waves = WCL_FUSED_MINWAVES;
 };
 
@@ -1273,6 +1322,91 @@ __global__ __launch_bounds__(NT, FusedShape<DOT>::min_waves) void k_blk_fused(Bl
             for (int k = 0; k < 24; ++k) rho[k] *= inv;
         }
     }
+    if constexpr (DOT) {
+        // own rho in registers (FP32); the neighbours read its binary16 pairs
+        h2v* s_rp = (h2v*)lds;               // [12][NT]
+        h2v* s_bw = (h2v*)(lds + 12 * NT);   // [4][6][NT]
+        for (int step = 0; step < a.B.n_dominv; ++step) {
+            F.refresh();
+            h2v rp[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                rp[k] = pack2(rho[2 * k], rho[2 * k + 1]);
+                s_rp[k * NT + l] = rp[k];
+            }
+            // publish the backward-hop contributions U_mu(x)^dag P+ rho(x)
+#define WCL_BWD16(MU)                                                           \
+    {                                                                           \
+        h2v hp[6], hs[6];                                                       \
+        float w[12];                                                            \
+        spin_project16<MU, false>(rp, hp, hs);                                  \
+        F.template apply16<MU, true>(hp, hs, w);                                \
+        _Pragma("unroll") for (int k = 0; k < 6; ++k)                           \
+            s_bw[(MU * 6 + k) * NT + l] = pack2(w[2 * k], w[2 * k + 1]);        \
+    }
+            WCL_BWD16(0) WCL_BWD16(1) WCL_BWD16(2) WCL_BWD16(3)
+#undef WCL_BWD16
+            __syncthreads();
+            // q = D_{Omega'} rho
+            float q[24];
+            F.site_term16(rp, rho, ck, q);
+#define WCL_HOPS16(MU)                                                                           \
+    if (nf[MU] >= 0) {                                                                           \
+        h2v np[12], hp[6], hs[6];                                                                \
+        float w[12];                                                                             \
+        _Pragma("unroll") for (int k = 0; k < 12; ++k) np[k] = s_rp[k * NT + nf[MU]];           \
+        spin_project16<MU, true>(np, hp, hs);                                                    \
+        F.template apply16<MU, false>(hp, hs, w);                                                \
+        spin_accumulate<MU, true>(w, mk * phf[MU], q);                                           \
+    }                                                                                            \
+    if (nb[MU] >= 0) {                                                                           \
+        float w[12];                                                                             \
+        _Pragma("unroll") for (int k = 0; k < 6; ++k) {                                          \
+            const h2v t = s_bw[(MU * 6 + k) * NT + nb[MU]];                                      \
+            w[2 * k] = (float)t.x;                                                               \
+            w[2 * k + 1] = (float)t.y;                                                           \
+        }                                                                                        \
+        spin_accumulate<MU, false>(w, mk * phb[MU], q);                                          \
+    }
+            WCL_HOPS16(0) WCL_HOPS16(1) WCL_HOPS16(2) WCL_HOPS16(3)
+#undef WCL_HOPS16
+            // <q, rho> and <q, q>: FP32 over the site's 12 components, FP64
+            // across the workgroup
+            double d[3] = {0.0, 0.0, 0.0};
+            if (active) {
+                float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    const float qr = q[2 * k], qi = q[2 * k + 1];
+                    const float rr = rho[2 * k], ri = rho[2 * k + 1];
+                    f0 = fmad(qr, rr, f0);
+                    f0 = fmad(qi, ri, f0);
+                    f1 = fmad(qr, ri, f1);
+                    f1 = fmad(-qi, rr, f1);
+                    f2 = fmad(qr, qr, f2);
+                    f2 = fmad(qi, qi, f2);
+                }
+                d[0] = f0;
+                d[1] = f1;
+                d[2] = f2;
+            }
+            // every thread has finished reading its neighbours' pairs after
+            // this barrier; the next writes of them come after it
+            wg_allreduce3<NT / 64>(d, s_red);
+            const float ar = d[2] > 0 ? (float)(d[0] / d[2]) : 0.f;
+            const float ai = d[2] > 0 ? (float)(d[1] / d[2]) : 0.f;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const float pr = rho[2 * k], pi = rho[2 * k + 1];
+                xs[2 * k] = fmad(ar, pr, xs[2 * k]);
+                xs[2 * k] = fmad(-ai, pi, xs[2 * k]);
+                xs[2 * k + 1] = fmad(ar, pi, xs[2 * k + 1]);
+                xs[2 * k + 1] = fmad(ai, pr, xs[2 * k + 1]);
+                rho[2 * k] = fmad(ai, q[2 * k + 1], fmad(-ar, q[2 * k], pr));
+                rho[2 * k + 1] = fmad(-ai, q[2 * k], fmad(-ar, q[2 * k + 1], pi));
+            }
+        }
+    } else {
     // rho lives in LDS between steps: only its owner thread writes it
 #pragma unroll
     for (int k = 0; k < 24; ++k) s_rho[k * NT + l] = rho[k];
@@ -1373,6 +1507,10 @@ __global__ __launch_bounds__(NT, FusedShape<DOT>::min_waves) void k_blk_fused(Bl
             s_rho[(2 * k + 1) * NT + l] = fmad(-ai, q[2 * k], fmad(-ar, q[2 * k + 1], pi));
         }
     }
+    // the final MR residual back in registers
+#pragma unroll
+    for (int k = 0; k < 24; ++k) rho[k] = s_rho[k * NT + l];
+    }   // FP32-operand steps
     // restriction to the owned sites and sum into the output
     if (!active || !block_owned(a.B, lc)) return;
     if constexpr (RES != 1) {
@@ -1380,7 +1518,7 @@ __global__ __launch_bounds__(NT, FusedShape<DOT>::min_waves) void k_blk_fused(Bl
             // this sweep's final MR residual, the next sweep's starting point
             float rn[24];
 #pragma unroll
-            for (int k = 0; k < 24; ++k) rn[k] = s_rho[k * NT + l] * scale;
+            for (int k = 0; k < 24; ++k) rn[k] = rho[k] * scale;
             SpinorIO<VP>::store((char*)a.rout + rhs * a.rout_stride, a.g.V, gi, rn);
         }
     }
