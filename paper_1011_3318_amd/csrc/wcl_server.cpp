@@ -86,6 +86,21 @@ uint64_t batch_key(const wcl_lattice* lat, const wcl_request& r, const wcl_solve
     return h | 1;
 }
 
+// the exact test behind an equal batch key: same lattice, couplings and
+// every solver parameter (the key only preselects)
+bool same_system(const Job& a, const Job& b) {
+    const wcl_solver_params &p = a.params, &q = b.params;
+    bool same = a.lat == b.lat && a.req.kappa == b.req.kappa && a.req.csw == b.req.csw &&
+                p.tol_outer == q.tol_outer && p.tol_inner == q.tol_inner && p.max_outer == q.max_outer &&
+                p.max_inner == q.max_inner && p.max_restarts == q.max_restarts && p.precond == q.precond &&
+                p.even_odd == q.even_odd && p.timers == q.timers && p.ras.s == q.ras.s &&
+                p.ras.n_ras == q.ras.n_ras && p.ras.n_dominv == q.ras.n_dominv && p.ras.storage == q.ras.storage &&
+                p.ras.kernel == q.ras.kernel && p.ras.block_solver == q.ras.block_solver &&
+                p.ras.schwarz == q.ras.schwarz && p.ras.arith == q.ras.arith;
+    for (int mu = 0; mu < 4; ++mu) same = same && p.ras.block[mu] == q.ras.block[mu];
+    return same;
+}
+
 // workspace key of a solve of nrhs right-hand sides
 uint64_t nrhs_key(uint64_t key, int nrhs) { return (key ^ (0x9e3779b97f4a7c15ull * (uint64_t)nrhs)) | 1; }
 
@@ -158,7 +173,7 @@ struct wcl_server {
             const Job& head = queue.front();
             std::vector<size_t> pick = {0};
             for (size_t q = 1; q < queue.size() && (int)pick.size() < max_batch; ++q)
-                if (queue[q].bkey == head.bkey) pick.push_back(q);
+                if (queue[q].bkey == head.bkey && same_system(queue[q], head)) pick.push_back(q);
             AdmitDecision d{};
             d.slot = -1;
             while (!pick.empty()) {
