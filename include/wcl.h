@@ -61,7 +61,8 @@ extern "C" {
 /* ---- precisions ---- */
 #define WCL_F64 0
 #define WCL_F32 1
-#define WCL_F16 2   /* binary16 storage, per-site FP32 scale for spinors/clover, FP32 arithmetic */
+#define WCL_F16 2   /* binary16 storage, per-site FP32 scale for spinors/clover; see wcl_apply_D and
+                       WCL_ARITH_* for the arithmetic on it */
 
 /* ---- RAS domain solver kernels ---- */
 #define WCL_BLOCK_AUTO 0
@@ -218,8 +219,13 @@ int wcl_unpack_spinor_dev(wcl_lattice* lat, int prec, int nrhs, const void* dev_
 /* ---- operators ---- */
 
 /* out = D in for nrhs fields (Eq. (1)), periodic lattice with the bc phases,
- * at storage precision prec for spinors, links and clover (arithmetic in
- * FP64 for WCL_F64, FP32 otherwise).  in and out must not alias. */
+ * at storage precision prec for spinors, links and clover.  Arithmetic: FP64
+ * for WCL_F64, FP32 for WCL_F32; for WCL_F16 the spin projections are
+ * binary16 additions of the stored values, the link and clover products take
+ * the stored binary16 values (and the projected half-spinors, rounded to
+ * binary16) as two-term dot products with FP32 sums, and the per-site scales
+ * and the accumulation are FP32 (relative error a few 1e-4).  in and out
+ * must not alias. */
 int wcl_apply_D(wcl_lattice* lat, int prec, double kappa, double csw, const void* in_dev, void* out_dev, int nrhs,
                 void* stream);
 

@@ -773,8 +773,6 @@ struct SiteFields {
 // values as widening them first).  Row 2 of each link is rebuilt once per
 // launch in FP32 and kept, instead of once per use.  This takes 85 registers
 // where FP32 copies of the fields take 120.
-typedef _Float16 h2v __attribute__((ext_vector_type(2)));
-
 template <>
 struct SiteFields<WCL_F16> {
     h2v u[4][6];      // rows 0,1 of U_mu(x), binary16
@@ -903,66 +901,16 @@ struct SiteFields<WCL_F16> {
     WCL_DEV void step_site_term(const float r[24], float ck, float q[24]) const { site_term(r, ck, q); }
 };
 
-// Complex products on packed binary16 pairs a = (ar, ai), b = (br, bi) with
-// b' = (bi, br), as two-term dot products with an FP32 sum (v_dot2_f32_f16:
-// both binary16 products are exact in FP32):
-//   Re(a b) = dot2n(a, b),  Im(a b) = dot2(a, b'),
-//   Re(conj(a) b) = dot2(a, b),  Im(conj(a) b) = dot2n(a, b').
-// dot2n negates the second product through the instruction's neg_hi
-// operand modifier (the compiler does not form it from the source).
-WCL_DEV float dot2(h2v a, h2v b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
-WCL_DEV float dot2n(h2v a, h2v b, float c) {
-    float d;
-    asm("v_dot2_f32_f16 %0, %1, %2, %3 neg_hi:[0,1,0]" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-    return d;
-}
-WCL_DEV h2v pack2(float x, float y) { return h2v{(_Float16)x, (_Float16)y}; }
-// (im, re) of a pair, and i z = (-im, re): the compiler folds both into the
-// operand modifiers of the packed binary16 add that uses them
-WCL_DEV h2v swp(h2v z) { return __builtin_shufflevector(z, z, 1, 0); }
-WCL_DEV h2v mul_i(h2v z) {
-    const h2v t = swp(z);
-    return h2v{-t.x, t.y};
-}
-
-// spin_project on a spinor held as 12 binary16 pairs (u0, u1, l0, l1 by
-// colour), in packed binary16 additions: hp = the half-spinor (h0, h1) as
-// pairs, hs the same pairs swapped (the operands of the v_dot2 products).
-template <int MU, bool FWD>
-WCL_DEV void spin_project16(const h2v s[12], h2v hp[6], h2v hs[6]) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const h2v u0 = s[c], u1 = s[3 + c], l0 = s[6 + c], l1 = s[9 + c];
-        h2v h0, h1;
-        if (MU == 0) {   // h0 = u0 +- i l1, h1 = u1 +- i l0
-            h0 = FWD ? u0 + mul_i(l1) : u0 - mul_i(l1);
-            h1 = FWD ? u1 + mul_i(l0) : u1 - mul_i(l0);
-        } else if (MU == 1) {   // h0 = u0 +- l1, h1 = u1 -+ l0
-            h0 = FWD ? u0 + l1 : u0 - l1;
-            h1 = FWD ? u1 - l0 : u1 + l0;
-        } else if (MU == 2) {   // h0 = u0 +- i l0, h1 = u1 -+ i l1
-            h0 = FWD ? u0 + mul_i(l0) : u0 - mul_i(l0);
-            h1 = FWD ? u1 - mul_i(l1) : u1 + mul_i(l1);
-        } else {   // h = u +- l
-            h0 = FWD ? u0 + l0 : u0 - l0;
-            h1 = FWD ? u1 + l1 : u1 - l1;
-        }
-        hp[c] = h0;
-        hp[3 + c] = h1;
-        hs[c] = swp(h0);
-        hs[3 + c] = swp(h1);
-    }
-}
-
 // FP16 storage with binary16 operands inside the MR steps: the fields as in
 // SiteFields<WCL_F16> (row 2 of each link rebuilt in FP32 at load and
-// rounded to binary16 as well), and each step's products of the links and
-// the clover with rho take rho rounded to binary16 (pairs (re, im) and
-// (im, re)) as v_dot2 operands, summed in FP32, and each site publishes its
-// backward-hop terms U^dag P+ rho as binary16 pairs (48 instead of 72 LDS
-// words per site).  Projections, accumulation and the MR vector work stay
-// FP32.  The kernel scales each domain's rho by a
-// power of two to an RMS component near 1 before the steps (MR commutes with
+// rounded to binary16 as well); each step's products of the links and the
+// clover take rho rounded to binary16 as v_dot2 operands (each pair as its
+// conjugate, swap or -i multiple, which carry the signs of the complex
+// product), summed in FP32, with the spin projections in packed binary16
+// additions, and the backward-hop terms U^dag P+ rho pass between sites as
+// binary16 pairs.  Accumulation and the MR vector work stay FP32.  The kernel
+// scales each domain's rho by a power of two to an RMS component near 1
+// before the steps (MR commutes with
 // the scaling), so the binary16 operands neither overflow nor lose precision
 // to small magnitudes.  The residual updates between sweeps use the
 // mixed-precision FMA forms (FP32 operands, unscaled).
@@ -1076,39 +1024,23 @@ struct SiteFieldsDot {
             for (int j = 0; j < 12; ++j) q[12 * bk + j] = fmad(f, y[j], x[j]);
         }
     }
-    // the same products with h rounded to binary16 (v_dot2)
+    // the same products with h rounded to binary16 (v_dot2): the operand
+    // pairs (conj h, swp h) of U h or (h, -i h) of U^dag h
     template <int MU, bool DAG>
     WCL_DEV void step_apply(const float h[12], float w[12]) const {
-        h2v hp[6], hs[6];
+        h2v ha[6], hb[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            hp[k] = pack2(h[2 * k], h[2 * k + 1]);
-            hs[k] = pack2(h[2 * k + 1], h[2 * k]);
+            const float re = h[2 * k], im = h[2 * k + 1];
+            ha[k] = DAG ? pack2(re, im) : pack2(re, -im);
+            hb[k] = DAG ? pack2(im, -re) : pack2(im, re);
         }
-        apply16<MU, DAG>(hp, hs, w);
+        apply16<MU, DAG>(ha, hb, w);
     }
-    // w = U h or U^dag h for h given as binary16 pairs hp and swapped pairs hs
+    // w = U h or U^dag h for h given as the operand pairs of spin_project16
     template <int MU, bool DAG>
-    WCL_DEV void apply16(const h2v hp[6], const h2v hs[6], float w[12]) const {
-#pragma unroll
-        for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                float re = zr, im = zr;
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    const h2v U = u[MU][DAG ? 3 * b + a : 3 * a + b];
-                    if (DAG) {
-                        re = dot2(U, hp[3 * sp + b], re);
-                        im = dot2n(U, hs[3 * sp + b], im);
-                    } else {
-                        re = dot2n(U, hp[3 * sp + b], re);
-                        im = dot2(U, hs[3 * sp + b], im);
-                    }
-                }
-                w[6 * sp + 2 * a] = re;
-                w[6 * sp + 2 * a + 1] = im;
-            }
+    WCL_DEV void apply16(const h2v ha[6], const h2v hb[6], float w[12]) const {
+        su3_apply16<DAG>(u[MU], ha, hb, zr, w);
     }
     WCL_DEV void step_site_term(const float r[24], float ck, float q[24]) const {
         h2v rp[12];
@@ -1123,12 +1055,7 @@ struct SiteFieldsDot {
         for (int bk = 0; bk < 2; ++bk) {
             const int o = 36 * bk;
             const float* x = r + 12 * bk;
-            h2v xp[6], xs[6];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                xp[k] = rp[6 * bk + k];
-                xs[k] = swp(xp[k]);
-            }
+            const h2v* xp = rp + 6 * bk;
             float y[12];
 #pragma unroll
             for (int a = 0; a < 6; ++a) {
@@ -1141,10 +1068,10 @@ struct SiteFieldsDot {
 #pragma unroll
                 for (int b = a + 1; b < 6; ++b, ++k) {
                     const h2v C = c[o / 2 + 3 + k];   // C_ab; C_ba = conj(C_ab)
-                    y[2 * a] = dot2n(C, xp[b], y[2 * a]);
-                    y[2 * a + 1] = dot2(C, xs[b], y[2 * a + 1]);
+                    y[2 * a] = dot2(C, cj(xp[b]), y[2 * a]);
+                    y[2 * a + 1] = dot2(C, swp(xp[b]), y[2 * a + 1]);
                     y[2 * b] = dot2(C, xp[a], y[2 * b]);
-                    y[2 * b + 1] = dot2n(C, xs[a], y[2 * b + 1]);
+                    y[2 * b + 1] = dot2(C, mul_mi(xp[a]), y[2 * b + 1]);
                 }
 #pragma unroll
             for (int j = 0; j < 12; ++j) q[12 * bk + j] = fmad(f, y[j], x[j]);
@@ -1332,15 +1259,19 @@ __global__ __launch_bounds__(NT, FusedShape<DOT>::min_waves) void k_blk_fused(Bl
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 rp[k] = pack2(rho[2 * k], rho[2 * k + 1]);
+                // opaque: the operand variants below come from the packed
+                // pair (folded into packed-add modifiers), not from
+                // re-converting rho's halves one by one
+                asm volatile("" : "+v"(rp[k]));
                 s_rp[k * NT + l] = rp[k];
             }
             // publish the backward-hop contributions U_mu(x)^dag P+ rho(x)
 #define WCL_BWD16(MU)                                                           \
     {                                                                           \
-        h2v hp[6], hs[6];                                                       \
+        h2v ha[6], hb[6];                                                       \
         float w[12];                                                            \
-        spin_project16<MU, false>(rp, hp, hs);                                  \
-        F.template apply16<MU, true>(hp, hs, w);                                \
+        spin_project16<MU, false, true>(rp, ha, hb);                            \
+        F.template apply16<MU, true>(ha, hb, w);                                \
         _Pragma("unroll") for (int k = 0; k < 6; ++k)                           \
             s_bw[(MU * 6 + k) * NT + l] = pack2(w[2 * k], w[2 * k + 1]);        \
     }
@@ -1352,11 +1283,11 @@ __global__ __launch_bounds__(NT, FusedShape<DOT>::min_waves) void k_blk_fused(Bl
             F.site_term16(rp, rho, ck, q);
 #define WCL_HOPS16(MU)                                                                           \
     if (nf[MU] >= 0) {                                                                           \
-        h2v np[12], hp[6], hs[6];                                                                \
+        h2v np[12], ha[6], hb[6];                                                                \
         float w[12];                                                                             \
         _Pragma("unroll") for (int k = 0; k < 12; ++k) np[k] = s_rp[k * NT + nf[MU]];           \
-        spin_project16<MU, true>(np, hp, hs);                                                    \
-        F.template apply16<MU, false>(hp, hs, w);                                                \
+        spin_project16<MU, true, false>(np, ha, hb);                                             \
+        F.template apply16<MU, false>(ha, hb, w);                                                \
         spin_accumulate<MU, true>(w, mk * phf[MU], q);                                           \
     }                                                                                            \
     if (nb[MU] >= 0) {                                                                           \

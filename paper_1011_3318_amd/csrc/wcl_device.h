@@ -443,6 +443,165 @@ WCL_DEV void spin_project(const T s[24], T h[12]) {
     }
 }
 
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+
+// Complex products on packed binary16 pairs z = (re, im) as v_dot2_f32_f16
+// (both binary16 products are exact in FP32, the sum is FP32).  Every
+// v_dot2 goes through the compiler builtin, none through inline asm: the
+// hardware needs wait states between a DOT instruction and a different
+// instruction that reads its result (or a DOT of another encoding reading
+// it), and only the compiler, knowing each such instruction, provides them.
+// The signs and the order of the two products sit in the second operand:
+//   Re(a b) = dot2(a, conj b),   Im(a b) = dot2(a, swp b),
+//   Re(conj(a) b) = dot2(a, b),  Im(conj(a) b) = dot2(a, -i b).
+WCL_DEV float dot2(h2v a, h2v b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
+WCL_DEV h2v pack2(float x, float y) { return h2v{(_Float16)x, (_Float16)y}; }
+// (im, re), conj z, i z and -i z of a pair: exact, and folded by the
+// compiler into the operand modifiers of the packed binary16 addition that
+// consumes them
+WCL_DEV h2v swp(h2v z) { return __builtin_shufflevector(z, z, 1, 0); }
+WCL_DEV h2v cj(h2v z) { return h2v{z.x, -z.y}; }
+WCL_DEV h2v mul_i(h2v z) { return h2v{-z.y, z.x}; }
+WCL_DEV h2v mul_mi(h2v z) { return h2v{z.y, -z.x}; }
+
+// The half-spinor h = (h0, h1) of spin_project<MU,FWD> for a spinor held as
+// 12 binary16 pairs (u0, u1, l0, l1 by colour), given as the operand pairs of
+// su3_apply16<DAG>: (conj h, swp h) for U h, (h, -i h) for U^dag h.  Each
+// pair is one packed binary16 addition u + y of the projection's two terms
+// with the conjugation, swap or -i applied to both (so the rounding is that
+// of h itself).
+template <int MU, bool FWD, bool DAG>
+WCL_DEV void spin_project16(const h2v s[12], h2v ha[6], h2v hb[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const h2v u0 = s[c], u1 = s[3 + c], l0 = s[6 + c], l1 = s[9 + c];
+        h2v y0, y1;
+        if (MU == 0) {   // h0 = u0 +- i l1, h1 = u1 +- i l0
+            y0 = FWD ? mul_i(l1) : mul_mi(l1);
+            y1 = FWD ? mul_i(l0) : mul_mi(l0);
+        } else if (MU == 1) {   // h0 = u0 +- l1, h1 = u1 -+ l0
+            y0 = FWD ? l1 : -l1;
+            y1 = FWD ? -l0 : l0;
+        } else if (MU == 2) {   // h0 = u0 +- i l0, h1 = u1 -+ i l1
+            y0 = FWD ? mul_i(l0) : mul_mi(l0);
+            y1 = FWD ? mul_mi(l1) : mul_i(l1);
+        } else {   // h = u +- l
+            y0 = FWD ? l0 : -l0;
+            y1 = FWD ? l1 : -l1;
+        }
+        if (DAG) {
+            ha[c] = u0 + y0;
+            ha[3 + c] = u1 + y1;
+            hb[c] = mul_mi(u0) + mul_mi(y0);
+            hb[3 + c] = mul_mi(u1) + mul_mi(y1);
+        } else {
+            ha[c] = cj(u0) + cj(y0);
+            ha[3 + c] = cj(u1) + cj(y1);
+            hb[c] = swp(u0) + swp(y0);
+            hb[3 + c] = swp(u1) + swp(y1);
+        }
+    }
+}
+
+// w = U h (DAG = false) or U^dag h, U as nine binary16 pairs (element (row,
+// col) at 3 row + col), h as the operand pairs (ha, hb) of spin_project16;
+// FP32 sums from the zero z (an opaque zero keeps the first product a v_dot2)
+template <bool DAG>
+WCL_DEV void su3_apply16(const h2v u[9], const h2v ha[6], const h2v hb[6], float z, float w[12]) {
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float re = z, im = z;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const h2v U = u[DAG ? 3 * b + a : 3 * a + b];
+                re = dot2(U, ha[3 * sp + b], re);
+                im = dot2(U, hb[3 * sp + b], im);
+            }
+            w[6 * sp + 2 * a] = re;
+            w[6 * sp + 2 * a + 1] = im;
+        }
+}
+
+// ------------------------------------------- FP16 storage on binary16 pairs
+// An FP16 spinor as stored: 12 binary16 pairs (re, im) of value / scale in
+// (spin, colour) order, and the per-site scale.
+WCL_DEV float load_spinor16(const void* base, int V, int i, h2v p[12]) {
+    const h8v* q = (const h8v*)base;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        const h8v v = q[tix(g, i, 3)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) p[4 * g + j] = h2v{v[2 * j], v[2 * j + 1]};
+    }
+    return ((const float*)((const char*)base + half_spinor_scale_offset(V)))[i];
+}
+
+// U_mu(site) from FP16 storage as nine binary16 pairs: rows 0, 1 as stored,
+// row 2 = conj(row0 x row1) from exact binary16 products summed in FP32 (z
+// an opaque zero), rounded to binary16.
+template <bool NT>
+WCL_DEV void load_link16(const void* gauge, int V, int mu, int site, float z, h2v u[9]) {
+    const h4v* gp = (const h4v*)gauge;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        const h4v v = ldx<NT>(gp + tix(3 * mu + g, site, 12));
+        u[2 * g] = h2v{v.x, v.y};
+        u[2 * g + 1] = h2v{v.z, v.w};
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int a = (c + 1) % 3, b = (c + 2) % 3;
+        // row0_a row1_b - row0_b row1_a, then the conjugate
+        const h2v nb = -u[b];
+        const float re = dot2(nb, cj(u[3 + a]), dot2(u[a], cj(u[3 + b]), z));
+        const float im = dot2(nb, swp(u[3 + a]), dot2(u[a], swp(u[3 + b]), z));
+        u[6 + c] = pack2(re, -im);
+    }
+}
+
+// acc = A(x) psi = sc psi + ck cs sc C psi: psi as stored (12 binary16 pairs,
+// scale sc), C the stored binary16 clover blocks (scale cs); the products
+// are exact binary16 products summed in FP32.
+template <bool NT>
+WCL_DEV void clover_site16(const void* base, int V, int i, const h2v x16[12], float sc, float ck, float z,
+                           float acc[24]) {
+    const h8v* p = (const h8v*)base;
+    h8v cv[9];
+#pragma unroll
+    for (int g = 0; g < 9; ++g) cv[g] = ldx<NT>(p + tix(g, i, 9));
+    const float f = ck * sc * ((const float*)((const char*)base + half_clover_scale_offset(V)))[i];
+#pragma unroll
+    for (int bk = 0; bk < 2; ++bk) {
+        // block bk: halves 36 bk + (6 diagonal reals, then 15 complex entries)
+        auto hv = [&](int k) { return cv[(36 * bk + k) / 8][(36 * bk + k) % 8]; };
+        const h2v* xp = x16 + 6 * bk;
+        float y[12];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            y[2 * a] = fmad((float)hv(a), (float)xp[a].x, z);
+            y[2 * a + 1] = fmad((float)hv(a), (float)xp[a].y, z);
+        }
+        int k = 0;
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+#pragma unroll
+            for (int b = a + 1; b < 6; ++b, ++k) {
+                const h2v C = h2v{hv(6 + 2 * k), hv(7 + 2 * k)};   // C_ab; C_ba = conj(C_ab)
+                y[2 * a] = dot2(C, cj(xp[b]), y[2 * a]);
+                y[2 * a + 1] = dot2(C, swp(xp[b]), y[2 * a + 1]);
+                y[2 * b] = dot2(C, xp[a], y[2 * b]);
+                y[2 * b + 1] = dot2(C, mul_mi(xp[a]), y[2 * b + 1]);
+            }
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            acc[12 * bk + 2 * a] = fmad(f, y[2 * a], fmad((float)xp[a].x, sc, z));
+            acc[12 * bk + 2 * a + 1] = fmad(f, y[2 * a + 1], fmad((float)xp[a].y, sc, z));
+        }
+    }
+}
+
 // acc += f * (w0, w1, lower(w)) for the projection spin_project<MU,FWD>.
 template <int MU, bool FWD, typename T>
 WCL_DEV void spin_accumulate(const T w[12], T f, T acc[24]) {
@@ -606,6 +765,17 @@ WCL_DEV void hop_compute(const S s[24], T u[18], T f, T acc[24]) {
     reconstruct_row2(u);
     spin_project<MU, FWD>(s, h);
     su3_apply2<!FWD>(u, h, w);
+    spin_accumulate<MU, FWD>(w, f, acc);
+}
+
+// One hop on binary16 pairs: s = the neighbour spinor as stored (value /
+// scale), u = the link, f = -kappa x phase x the neighbour's scale.
+template <int MU, bool FWD>
+WCL_DEV void hop_compute16(const h2v s[12], const h2v u[9], float f, float z, float acc[24]) {
+    h2v ha[6], hb[6];
+    float w[12];
+    spin_project16<MU, FWD, !FWD>(s, ha, hb);
+    su3_apply16<!FWD>(u, ha, hb, z, w);
     spin_accumulate<MU, FWD>(w, f, acc);
 }
 

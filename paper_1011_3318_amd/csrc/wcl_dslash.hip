@@ -73,6 +73,46 @@ WCL_DEV void dslash_site(const DslashArgs& a, const char* in, int i, T acc[24]) 
     hop_chain<0, D, NT, GP, SPI>(a, in, nbr, lnk, ph, T(-a.kappa), sb, ss, ub, acc);
 }
 
+// FP16 storage: the same pipeline on binary16 pairs (the neighbour spinor as
+// stored and its scale, the link with row 2 rebuilt from exact binary16
+// products), every hop formed by packed binary16 projections and v_dot2
+// products with FP32 sums (hop_compute16).
+template <int K, int D, bool NT>
+WCL_DEV void hop_chain16(const DslashArgs& a, const char* in, const int nbr[8], const int lnk[8], const float ph[8],
+                         float mk, float z, h2v sb[D][12], float ss[D], h2v ub[D][9], float acc[24]) {
+    if constexpr (K < 8) {
+        constexpr int slot = K % D;
+        hop_compute16<K / 2, (K % 2) == 0>(sb[slot], ub[slot], mk * ph[K] * ss[slot], z, acc);
+        if constexpr (K + D < 8) {
+            ss[slot] = load_spinor16(in, a.g.V, nbr[K + D], sb[slot]);
+            load_link16<NT>(a.gauge, a.g.V, (K + D) / 2, lnk[K + D], z, ub[slot]);
+        }
+        hop_chain16<K + 1, D, NT>(a, in, nbr, lnk, ph, mk, z, sb, ss, ub, acc);
+    }
+}
+
+template <bool NT>
+WCL_DEV void dslash_site16(const DslashArgs& a, const char* in, int i, float acc[24]) {
+    constexpr int D = WCL_PIPE_DEPTH;
+    int x[4], nbr[8], lnk[8];
+    float ph[8];
+    geom_coords(a.g, i, x);
+    hop_sites(a.g, i, x, nbr, lnk, ph);
+    float z = 0.f;   // opaque zero: the first product of every chain stays a v_dot2
+    asm volatile("" : "+v"(z));
+    h2v sb[D][12], ub[D][9];
+    float ss[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        ss[k] = load_spinor16(in, a.g.V, nbr[k], sb[k]);
+        load_link16<NT>(a.gauge, a.g.V, k / 2, lnk[k], z, ub[k]);
+    }
+    h2v x16[12];
+    const float sc = load_spinor16(in, a.g.V, i, x16);
+    clover_site16<NT>(a.clover, a.g.V, i, x16, sc, (float)(a.csw * a.kappa), z, acc);
+    hop_chain16<0, D, NT>(a, in, nbr, lnk, ph, (float)(-a.kappa), z, sb, ss, ub, acc);
+}
+
 template <int GP, int SPI, int SPO, int EPI, int SPY, bool NT>
 #ifndef WCL_DSLASH_MINWAVES
 #define WCL_DSLASH_MINWAVES 1
@@ -87,7 +127,10 @@ __global__ __launch_bounds__(256, WCL_DSLASH_MINWAVES) void k_dslash(DslashArgs 
     const bool active = i < a.g.V;
     T acc[24];
     if (active) {
-        dslash_site<NT, GP, SPI>(a, (const char*)a.in + rhs * a.in_stride, i, acc);
+        if constexpr (GP == WCL_F16 && SPI == WCL_F16)
+            dslash_site16<NT>(a, (const char*)a.in + rhs * a.in_stride, i, acc);
+        else
+            dslash_site<NT, GP, SPI>(a, (const char*)a.in + rhs * a.in_stride, i, acc);
         if (EPI == DS_AXPY) {
             T y[24];
             SpinorIO<SPY>::load((const char*)a.y + rhs * a.y_stride, a.g.V, i, y);
@@ -290,6 +333,153 @@ __global__ __launch_bounds__(256, WCL_XY_MINWAVES) void k_dslash_xy(DslashArgs a
     }
 }
 
+// The exchange kernel for FP16 storage on binary16 pairs: the lanes exchange
+// conj(P- psi(s)) as stored pairs (6 words) and U_mu(s)^dag P+ psi(s) in FP32 (12
+// words), each with the sender's scale, which joins the receiver's hop
+// factor; the products are v_dot2 on pairs, the accumulation FP32.
+WCL_DEV h2v lane_fetch16(h2v v, int src) {
+    return __builtin_bit_cast(h2v, __builtin_amdgcn_ds_bpermute(src << 2, __builtin_bit_cast(int, v)));
+}
+
+template <int SPO, int EPI, int SPY, bool NT>
+__global__ __launch_bounds__(256, WCL_XY_MINWAVES) void k_dslash_xy16(DslashArgs a) {
+    __shared__ h2v hf_y[6][256];     // conj of P- psi(s), stored pairs: forward y hop of the row below
+    __shared__ float hb_y[12][256];  // U_y(s)^dag P+ psi(s) (unscaled): backward y hop of the row above
+    __shared__ float sc_y[256];      // psi(s)'s scale
+    const Geom& g = a.g;
+    const int V = g.V;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int rhs = lb % a.nrhs;
+    if (a.sc && !a.sc[rhs].active) return;   // uniform over the workgroup
+    const int t = threadIdx.x;
+    const int i = (lb / a.nrhs) * 256 + t;   // V % 256 == 0: every lane has a site
+    const char* in = (const char*)a.in + rhs * a.in_stride;
+    const int R = g.c[0], NR = 256 / R;      // lanes per x row, rows per workgroup
+    const int r = t >> g.lc[0];
+    int x[4], nbr[8], lnk[8];
+    float ph[8];
+    geom_coords(g, i, x);
+    hop_sites(g, i, x, nbr, lnk, ph);
+    const float mk = (float)(-a.kappa);
+    float z = 0.f;   // opaque zero: the first product of every chain stays a v_dot2
+    asm volatile("" : "+v"(z));
+
+    h2v psi[12], uy[9];
+    const float sc = load_spinor16(in, V, i, psi);
+    load_link16<NT>(a.gauge, V, 1, i, z, uy);
+    {
+        h2v ha[6], hb[6];
+        float w[12];
+        spin_project16<1, true, false>(psi, ha, hb);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) hf_y[k][t] = ha[k];
+        sc_y[t] = sc;
+        spin_project16<1, false, true>(psi, ha, hb);
+        su3_apply16<true>(uy, ha, hb, z, w);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) hb_y[k][t] = w[k];
+    }
+    WCL_PHASE();
+
+    // x hops through the wavefront
+    float wf[12], wb[12], s_up, s_dn;
+    {
+        h2v ux[9], ha[6], hb[6], hr[6], hrs[6];
+        load_link16<NT>(a.gauge, V, 0, i, z, ux);
+        const int lane = t & 63, row0 = lane & ~(R - 1);
+        const int up = row0 | ((lane + 1) & (R - 1)), dn = row0 | ((lane + R - 1) & (R - 1));
+        // conj h travels; swp h = i conj h
+        spin_project16<0, true, false>(psi, ha, hb);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            hr[k] = lane_fetch16(ha[k], up);
+            hrs[k] = mul_i(hr[k]);
+        }
+        s_up = lane_fetch(sc, up);
+        s_dn = lane_fetch(sc, dn);
+        su3_apply16<false>(ux, hr, hrs, z, wf);
+        float w[12];
+        spin_project16<0, false, true>(psi, ha, hb);
+        su3_apply16<true>(ux, ha, hb, z, w);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) wb[k] = lane_fetch(w[k], dn);
+    }
+    WCL_PHASE();
+
+    float acc[24];
+    clover_site16<NT>(a.clover, V, i, psi, sc, (float)(a.csw * a.kappa), z, acc);
+    WCL_PHASE();
+    spin_accumulate<0, true>(wf, mk * ph[0] * s_up, acc);
+    spin_accumulate<0, false>(wb, mk * ph[1] * s_dn, acc);
+    pin_values(acc);   // finish the site term and x hops before the barrier
+
+    // y hops from LDS; the edge rows of a workgroup that does not span y load
+    __syncthreads();
+    const bool wrap = NR == g.L[1];
+    {
+        h2v ha[6], hb[6];
+        float w[12], sy;
+        if (r + 1 < NR || wrap) {
+            const int src = r + 1 < NR ? t + R : t - (NR - 1) * R;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                ha[k] = hf_y[k][src];
+                hb[k] = mul_i(ha[k]);
+            }
+            sy = sc_y[src];
+        } else {
+            h2v sn[12];
+            sy = load_spinor16(in, V, nbr[2], sn);
+            spin_project16<1, true, false>(sn, ha, hb);
+        }
+        su3_apply16<false>(uy, ha, hb, z, w);
+        spin_accumulate<1, true>(w, mk * ph[2] * sy, acc);
+    }
+    {
+        float w[12], sy;
+        if (r > 0 || wrap) {
+            const int src = r > 0 ? t - R : t + (NR - 1) * R;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) w[k] = hb_y[k][src];
+            sy = sc_y[src];
+        } else {
+            h2v sn[12], u[9], ha[6], hb[6];
+            sy = load_spinor16(in, V, nbr[3], sn);
+            load_link16<NT>(a.gauge, V, 1, lnk[3], z, u);
+            spin_project16<1, false, true>(sn, ha, hb);
+            su3_apply16<true>(u, ha, hb, z, w);
+        }
+        spin_accumulate<1, false>(w, mk * ph[3] * sy, acc);
+    }
+
+    WCL_PHASE();
+    // z and t hops: the pipelined neighbour loads
+    constexpr int D = WCL_PIPE_DEPTH;
+    h2v sb[D][12], ub[D][9];
+    float ss[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        ss[(4 + k) % D] = load_spinor16(in, V, nbr[4 + k], sb[(4 + k) % D]);
+        load_link16<NT>(a.gauge, V, (4 + k) / 2, lnk[4 + k], z, ub[(4 + k) % D]);
+    }
+    hop_chain16<4, D, NT>(a, in, nbr, lnk, ph, mk, z, sb, ss, ub, acc);
+
+    if (EPI == DS_AXPY) {
+        float y[24];
+        SpinorIO<SPY>::load((const char*)a.y + rhs * a.y_stride, V, i, y);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[k] = y[k] - acc[k];
+    }
+    SpinorIO<SPO>::store((char*)a.out + rhs * a.out_stride, V, i, acc);
+    if (EPI == DS_DOT) {
+        double d[3] = {0.0, 0.0, 0.0};
+        float v[24];
+        SpinorIO<SPO>::load((const char*)a.a + rhs * a.a_stride, V, i, v);
+        site_dot3(v, acc, d);
+        block_reduce3(d, a.partial + 3 * (size_t)((lb / a.nrhs) + (size_t)rhs * (gridDim.x / a.nrhs)));
+    }
+}
+
 // ------------------------------------------------ several lanes per site
 // Stores the float groups of s that belong to `lane` of LPS lanes.
 template <int P>
@@ -444,8 +634,13 @@ static int launch_t(const DslashArgs& a, hipStream_t st) {
             // 256 MB Infinity Cache holds
             const bool nt = a.nrhs == 1 && dslash_launch_bytes(a.g.V, GP, SPI, SPO) > (256u << 20);
             if (dslash_xy_layout(a.g)) {
-                if (nt) k_dslash_xy<GP, SPI, SPO, EPI, SPY, true><<<tiles * a.nrhs, 256, 0, st>>>(a);
-                else k_dslash_xy<GP, SPI, SPO, EPI, SPY, false><<<tiles * a.nrhs, 256, 0, st>>>(a);
+                if constexpr (GP == WCL_F16 && SPI == WCL_F16) {
+                    if (nt) k_dslash_xy16<SPO, EPI, SPY, true><<<tiles * a.nrhs, 256, 0, st>>>(a);
+                    else k_dslash_xy16<SPO, EPI, SPY, false><<<tiles * a.nrhs, 256, 0, st>>>(a);
+                } else {
+                    if (nt) k_dslash_xy<GP, SPI, SPO, EPI, SPY, true><<<tiles * a.nrhs, 256, 0, st>>>(a);
+                    else k_dslash_xy<GP, SPI, SPO, EPI, SPY, false><<<tiles * a.nrhs, 256, 0, st>>>(a);
+                }
             } else if (nt) {
                 k_dslash<GP, SPI, SPO, EPI, SPY, true><<<tiles * a.nrhs, 256, 0, st>>>(a);
             } else {

@@ -56,3 +56,22 @@ def test_null_arguments_rejected(lib):
     lib.wcl_spinor_bytes.restype = C.c_uint64
     lib.wcl_spinor_bytes.argtypes = [C.c_void_p, C.c_int, C.c_int]
     assert lib.wcl_spinor_bytes(None, 1, 1) == 0
+
+
+def test_no_dot_instruction_in_inline_asm():
+    """Every two-term binary16 product is issued through the compiler builtin,
+    none through inline asm.  A DOT instruction needs wait states before a
+    different instruction reads its result (or a DOT of another encoding
+    takes it as its accumulator), and the compiler provides them only around
+    instructions it generates itself: an inline-asm v_dot2 scheduled next to
+    its reader has produced wrong link products."""
+    csrc = os.path.join(ROOT, "paper_1011_3318_amd", "csrc")
+    bad = []
+    for name in sorted(os.listdir(csrc)):
+        if not name.endswith((".hip", ".h", ".cpp")):
+            continue
+        src = open(os.path.join(csrc, name)).read()
+        for m in re.finditer(r"\basm\b\s*(?:volatile\s*)?\((.*?)\)\s*;", src, flags=re.S):
+            if re.search(r"v_dot|v_mfma|v_smfmac", m.group(1)):
+                bad.append((name, src.count("\n", 0, m.start()) + 1))
+    assert not bad, bad

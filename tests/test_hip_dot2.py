@@ -67,8 +67,9 @@ def test_ras_dot2_matches_oracle(W, ctx, dims, block, s, n_ras, nd):
     e2 = rel_err(got, lat.unpack(v2, W.F32))
     print(f"dot2 RAS rel err vs oracle {e:.2e}, vs FP32-arithmetic steps {e2:.2e}")
     assert np.isfinite(got).all()
-    assert e <= 2e-2
-    assert e2 <= 1e-2
+    # measured 1.3e-4 .. 2.7e-4 for both on these cases
+    assert e <= 2e-3
+    assert e2 <= 2e-3
     lat.close()
 
 
@@ -105,7 +106,7 @@ def test_ras_dot2_zero_and_point_sources(W, ctx):
     got = lat.unpack(v, W.F32)
     ref = Oracle(dims, U).ras(eta[4], 0.125, 1.0, (4, 4, 4, 4), 0, 2, 4)
     assert np.isfinite(got).all()
-    assert rel_err(got, ref) <= 2e-2
+    assert rel_err(got, ref) <= 5e-3
     lat.close()
 
 

@@ -9,7 +9,7 @@ from paper_1011_3318_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-13, 1: 1e-5, 2: 5e-3}   # FP64, FP32, FP16 (relative L2)
+TOL = {0: 1e-13, 1: 1e-5, 2: 2e-3}   # FP64, FP32, FP16 (relative L2; FP16 measured 2.9e-4)
 
 
 @pytest.fixture(scope="module")
