@@ -102,9 +102,12 @@ MR_FLOPS = 96 + 48 + 96 + 96
 
 
 def source_hash(files) -> str:
-    """Hash of the kernel sources with comments and blank lines removed, so
-    that a comment edit does not invalidate the stored counter runs."""
+    """Hash of the kernel sources with comments and blank lines removed (so
+    that a comment edit does not invalidate the stored counter runs) and of
+    the device compiler flags (include paths aside)."""
+    from paper_1011_3318_amd import build
     h = hashlib.sha256()
+    h.update(" ".join(f for f in build.HIPCC_FLAGS if not f.startswith("-I")).encode() + b"\n")
     for f in files:
         with open(os.path.join(ROOT, "paper_1011_3318_amd", "csrc", f)) as fh:
             text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
@@ -158,7 +161,7 @@ def event_time_us(torch, fn, n):
     return s.elapsed_time(e) / n * 1e3
 
 
-def time_dapply(torch, I, lat, prec, nrhs=1, n_warm=10, n_timed=100):
+def time_dapply(torch, I, lat, prec, nrhs=1, n_warm=10, n_timed=300):
     """D-apply timing: three input and three output copies rotated so that no
     launch starts with its operands in cache."""
     import numpy as np

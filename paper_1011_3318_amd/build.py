@@ -24,6 +24,9 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed-FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no two-address v_dot2c_f32_f16: the three-address v_dot2_f32_f16 starts
+    # each product chain from a shared zero without copying it first
+    "-Xclang", "-target-feature", "-Xclang", "-dot5-insts",
     "-ffp-contract=fast", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ] + os.environ.get("WCL_HIPCC_EXTRA", "").split()

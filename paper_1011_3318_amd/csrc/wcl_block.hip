@@ -1259,12 +1259,13 @@ __global__ __launch_bounds__(NT, FusedShape<DOT>::min_waves) void k_blk_fused(Bl
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 rp[k] = pack2(rho[2 * k], rho[2 * k + 1]);
-                // opaque: the operand variants below come from the packed
-                // pair (folded into packed-add modifiers), not from
-                // re-converting rho's halves one by one
-                asm volatile("" : "+v"(rp[k]));
                 s_rp[k * NT + l] = rp[k];
             }
+            // opaque: the operand variants below come from the packed pairs
+            // (folded into packed-add modifiers), not from re-converting
+            // rho's halves one by one
+#pragma unroll
+            for (int k = 0; k < 12; ++k) asm volatile("" : "+v"(rp[k]));
             // publish the backward-hop contributions U_mu(x)^dag P+ rho(x)
 #define WCL_BWD16(MU)                                                           \
     {                                                                           \
