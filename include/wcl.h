@@ -92,9 +92,10 @@ typedef struct wcl_server wcl_server;
 #define WCL_ARITH_FP32 0   /* FP32 FMAs on the stored fields (binary16 fields widened inside the FMAs) */
 #define WCL_ARITH_DOT2 1   /* the link and clover products of each MR step take the domain residual
                               rounded to binary16 (after scaling the domain by a power of two to an RMS
-                              component near 1) and sum in FP32 (two-term dot products), and the
-                              backward-hop terms pass between sites as binary16; projections,
-                              accumulation, the MR scalars and vector updates stay FP32.  FP16 storage,
+                              component near 1) and sum in FP32 (two-term dot products), the spin
+                              projections are binary16 additions of those values, and the
+                              backward-hop terms pass between sites as binary16; accumulation, the MR
+                              scalars and vector updates stay FP32.  FP16 storage,
                               MR domain solver, RAS, extended domains of at most 256 sites only
                               (WCL_EINVAL otherwise).  The preconditioner stays homogeneous:
                               K(2^k r) = 2^k K(r) exactly */
