@@ -719,6 +719,27 @@ WCL_DEV void wg_allreduce3(double d[3], double* sh) {
     }
 }
 
+// The same for FP32 per-thread values: FP32 over each wavefront, FP64
+// across the wavefronts, in a fixed order.
+template <int NW>
+WCL_DEV void wg_allreduce3f(const float f[3], double d[3], double* sh) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    float s[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s[k] = wave_sumf(f[k]);
+    if (l == 0)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sh[3 * w + k] = (double)s[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double r = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) r += sh[3 * q + k];
+        d[k] = r;
+    }
+}
+
 // Links U_mu(x) (rows 0, 1) and the clover block pair of one site, held in
 // registers (as FP32) for all MR steps.  Cached loads: every sweep of every
 // inner iteration reads them again, and at moderate volumes they stay in the
@@ -1302,29 +1323,26 @@ __global__ __launch_bounds__(NT, FusedShape<DOT>::min_waves) void k_blk_fused(Bl
     }
             WCL_HOPS16(0) WCL_HOPS16(1) WCL_HOPS16(2) WCL_HOPS16(3)
 #undef WCL_HOPS16
-            // <q, rho> and <q, q>: FP32 over the site's 12 components, FP64
-            // across the workgroup
-            double d[3] = {0.0, 0.0, 0.0};
+            // <q, rho> and <q, q>: FP32 over the site's 12 components and
+            // over each wavefront, FP64 across the wavefronts
+            float f[3] = {0.f, 0.f, 0.f};
             if (active) {
-                float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 #pragma unroll
                 for (int k = 0; k < 12; ++k) {
                     const float qr = q[2 * k], qi = q[2 * k + 1];
                     const float rr = rho[2 * k], ri = rho[2 * k + 1];
-                    f0 = fmad(qr, rr, f0);
-                    f0 = fmad(qi, ri, f0);
-                    f1 = fmad(qr, ri, f1);
-                    f1 = fmad(-qi, rr, f1);
-                    f2 = fmad(qr, qr, f2);
-                    f2 = fmad(qi, qi, f2);
+                    f[0] = fmad(qr, rr, f[0]);
+                    f[0] = fmad(qi, ri, f[0]);
+                    f[1] = fmad(qr, ri, f[1]);
+                    f[1] = fmad(-qi, rr, f[1]);
+                    f[2] = fmad(qr, qr, f[2]);
+                    f[2] = fmad(qi, qi, f[2]);
                 }
-                d[0] = f0;
-                d[1] = f1;
-                d[2] = f2;
             }
+            double d[3];
             // every thread has finished reading its neighbours' pairs after
             // this barrier; the next writes of them come after it
-            wg_allreduce3<NT / 64>(d, s_red);
+            wg_allreduce3f<NT / 64>(f, d, s_red);
             const float ar = d[2] > 0 ? (float)(d[0] / d[2]) : 0.f;
             const float ai = d[2] > 0 ? (float)(d[1] / d[2]) : 0.f;
 #pragma unroll

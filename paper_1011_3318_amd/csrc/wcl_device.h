@@ -860,6 +860,23 @@ WCL_DEV double wave_sum(double v) {
     return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 
+// The same butterflies in FP32 (the compiler fuses each move into the add
+// that takes it, v_add_f32 with a DPP operand), then the four row sums.
+template <int CTRL>
+WCL_DEV float dpp_movef(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+WCL_DEV float lane_readf(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+WCL_DEV float wave_sumf(float v) {
+    v += dpp_movef<0xB1>(v);
+    v += dpp_movef<0x4E>(v);
+    v += dpp_movef<0x141>(v);
+    v += dpp_movef<0x140>(v);
+    return (lane_readf(v, 0) + lane_readf(v, 16)) + (lane_readf(v, 32) + lane_readf(v, 48));
+}
+
 // Sum of d[0..2] over the workgroup (up to 1024 threads) in a fixed order;
 // thread 0 writes the three sums to out.
 WCL_DEV void block_reduce3(double d[3], double* out) {
