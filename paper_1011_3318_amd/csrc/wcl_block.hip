@@ -1343,8 +1343,9 @@ __global__ __launch_bounds__(NT, FusedShape<DOT>::min_waves) void k_blk_fused(Bl
             // every thread has finished reading its neighbours' pairs after
             // this barrier; the next writes of them come after it
             wg_allreduce3f<NT / 64>(f, d, s_red);
-            const float ar = d[2] > 0 ? (float)(d[0] / d[2]) : 0.f;
-            const float ai = d[2] > 0 ? (float)(d[1] / d[2]) : 0.f;
+            // alpha = <q, rho> / <q, q>: one FP64 reciprocal for both parts
+            const double inv = d[2] > 0 ? 1.0 / d[2] : 0.0;
+            const float ar = (float)(d[0] * inv), ai = (float)(d[1] * inv);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 const float pr = rho[2 * k], pi = rho[2 * k + 1];
