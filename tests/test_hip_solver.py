@@ -66,6 +66,7 @@ RAS_CASES = [
     ((8, 8, 8, 8), (4, 4, 4, 4), 1, 3, 4),     # split (ev = 1296)
     ((8, 4, 6, 4), (4, 2, 2, 4), 1, 2, 5),     # split
     ((16, 8, 8, 8), (8, 8, 8, 8), 1, 1, 3),    # split, the 8^4 domains of the 16^3x32 benchmark
+    ((16, 16, 8, 8), (8, 8, 4, 4), 1, 2, 3),   # split; the residual update runs the x/y exchange D-apply
     ((8, 8, 8, 8), (4, 4, 4, 4), 0, 4, 3),     # fused, 4 sweeps: the v_j / rho_N buffers are reused
     ((8, 8, 8, 8), (2, 2, 2, 2), 1, 4, 2),     # fused, overlap, 4 sweeps: r_j buffers reused
 ]
