@@ -1,5 +1,6 @@
-"""Host-side checks of the benchmark script (no GPU): the multi-GPU refusal
-and the algorithmic flop count used for the domain-solver roofline."""
+"""Host-side checks of the benchmark script (no GPU): the multi-GPU refusal,
+the algorithmic flop count used for the domain-solver roofline, and the hash
+that ties the stored HBM counters to the kernel sources and flags."""
 import importlib.util
 import os
 import subprocess
@@ -48,3 +49,23 @@ def test_valu_peak_from_unit_counts():
     b = load_bench()
     # 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
     assert abs(b.VALU_F32_PEAK_TFLOPS - 78.6432) < 1e-3
+
+
+def test_counter_hash_follows_sources_and_flags():
+    """The stored HBM counters count as this build's only while the hash of
+    the kernel sources (comments aside) and the device compiler flags is
+    unchanged: a flag that changes the code changes the hash, a comment does
+    not."""
+    b = load_bench()
+    from paper_1011_3318_amd import build
+    h0 = b.source_hash(b.DOMAIN_SOURCES)
+    assert h0 == b.source_hash(b.DOMAIN_SOURCES)
+    assert h0 != b.source_hash(b.DAPPLY_SOURCES)
+    saved = list(build.HIPCC_FLAGS)
+    try:
+        build.HIPCC_FLAGS.append("-DWCL_SOME_SWITCH=1")
+        assert b.source_hash(b.DOMAIN_SOURCES) != h0
+        build.HIPCC_FLAGS[:] = saved + [f"-I{ROOT}/elsewhere"]   # include paths do not count
+        assert b.source_hash(b.DOMAIN_SOURCES) == h0
+    finally:
+        build.HIPCC_FLAGS[:] = saved
